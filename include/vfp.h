@@ -1,0 +1,192 @@
+/*
+ * vfp.h -- C ABI of libvfp.so, an MI355X (gfx950) implementation of one time
+ * step of the discretised Vlasov-Fokker-Planck split map of Schoenfeldt et
+ * al., "A Parallelized Vlasov-Fokker-Planck-Solver for Desktop PCs"
+ * (arXiv:1611.05293).
+ *
+ * The state is the longitudinal phase-space density psi(q, p) on an n x n
+ * node grid (Sec. III.A, Eq. "coordinate trafo"): q_i = q_min + i*dq,
+ * p_j = p_min + j*dp, dq = (q_max - q_min)/(n - 1), dp likewise.  Every
+ * psi array crossing this ABI is row-major psi[i*n + j] with the p index j
+ * fastest (Sec. III.B: z = N_y*x + y), FP64, in host memory.
+ *
+ * One step (Sec. III.B, f = f_rot + f_kick + f_damp,diff) with
+ * dtheta = 2*pi/steps_per_period radians:
+ *   1. profile   rho_i = dp * sum_j psi_ij                      (Sec. II.B)
+ *   2. wake      V_i = S * sum_j w[(i - j) mod M] rho_j,
+ *                w[l] = (1/M) sum_k Z_k e^{+2 pi i k l/M}     (Eq. "wakepotential")
+ *   3. rotation  pull from (q c - p s, q s + p c), c = cos dtheta, s = sin dtheta,
+ *                K x K Lagrange interpolation (standard), or the Manhattan
+ *                drift + RF kick pair of 1-D interpolations      (Sec. III.A-B)
+ *   4. kick      pull along p from p + V_i * dtheta              (Sec. III.B)
+ *   5. damping/diffusion  psi += beta*dtheta * [D1(p psi) + D2 psi], D1 the
+ *                derivative of the cubic interpolant (Eq. "cubic diff"),
+ *                D2 the 3-point second difference; zero outside the grid
+ *   6. renormalisation of the charge dq*dp*sum(psi) to its initial value Q0
+ *                (optional; FP64 on the device).
+ * rho and V are taken from psi at the start of the step (the collective
+ * force is constant over a small step, Sec. II.A).
+ *
+ * Threading and ownership: a handle is used from one host thread at a time.
+ * Every array passed in is deep-copied before the call returns; output
+ * arrays are caller-owned host memory of the stated size.  A workspace, if
+ * given, is device memory of at least vfp_workspace_size() bytes that must
+ * outlive the handle; with ws == NULL the library allocates and frees its
+ * own.  The stream is the caller's hipStream_t; with NULL the handle creates
+ * a non-blocking stream of its own (graphs cannot be captured on the null
+ * stream).
+ * Stepping calls only enqueue work on that stream; the query calls
+ * (profile, csr_power, moments, get_psi, read_record) synchronise it.
+ *
+ * Errors: every int-returning call returns one of the VFP_* codes and never
+ * aborts; vfp_last_error() returns a thread-local description of the last
+ * failure.  Invalid parameters are rejected at create time.
+ */
+#ifndef VFP_H
+#define VFP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    VFP_OK = 0,
+    VFP_EINVAL = -1,     /* invalid argument                                  */
+    VFP_ENOMEM = -2,     /* device allocation failed or workspace too small   */
+    VFP_EDEVICE = -3,    /* HIP runtime error, or non-finite state detected    */
+    VFP_ESTATE = -4,     /* call not valid in the handle's current state       */
+    VFP_EUNSTABLE = -5   /* explicit damping step unstable for these settings  */
+};
+
+/* Arithmetic of psi and of the wake (Sec. IV.A compares binary32/binary64). */
+enum {
+    VFP_FP64 = 0,        /* psi, rotation, kick, damping and wake in FP64          */
+    VFP_FP32 = 1,        /* psi and the step in FP32, wake FP32 on the vector ALU  */
+    VFP_MIXED_BF16 = 2,  /* psi FP32; wake on BF16 matrix cores, hi/lo split       */
+    VFP_MIXED_FP16 = 3   /* psi FP32; wake on FP16 matrix cores, hi/lo split       */
+};
+/* Charge renormalisation, moments and CSR power are FP64 in every mode. */
+
+enum {
+    VFP_ROT_STANDARD = 0,   /* 2-D K x K tensor interpolation (Sec. III.B)        */
+    VFP_ROT_MANHATTAN = 1   /* drift then RF kick, two 1-D interpolations         */
+};
+
+typedef struct vfp_params {
+    int32_t n;                /* grid points per axis, 16..4096                    */
+    double  q_min, q_max;     /* node range in q (bunch length units)              */
+    double  p_min, p_max;     /* node range in p (energy spread units)             */
+    int32_t steps_per_period; /* >= 1; dtheta = 2*pi/steps_per_period               */
+    double  beta;             /* damping/diffusion coefficient per radian, >= 0    */
+    int32_t interp;           /* K = 3 (quadratic) or 4 (cubic), Sec. III.A        */
+    int32_t clamp;            /* 1: clip interpolants to the bracketing nodes'
+                                 range (Eq. "clamping"); 0: plain interpolation  */
+    int32_t renormalize;      /* 1: keep the charge at Q0 each step                */
+    int32_t precision;        /* VFP_FP64 / VFP_FP32 / VFP_MIXED_*                  */
+    int32_t padding;          /* M = padding*n wake samples, >= 2                   */
+    int32_t rotation;         /* VFP_ROT_*                                          */
+    const double *z_re;       /* floor(M/2)+1 impedance samples Z_k, k = 0..M/2 at  */
+    const double *z_im;       /* kappa_k = 2*pi*k/(M*dq); both NULL: zero current.  */
+                              /* Im Z_0 and Im Z_{M/2} are ignored (Hermitian).     */
+    double  z_scale;          /* S in V = S * (w conv rho) (normalised current)    */
+    const double *psi0;       /* n*n initial density; NULL: unit Gaussian          */
+    int64_t max_steps;        /* batch only: the simulation stops advancing after
+                                 this many steps (0: never)                        */
+} vfp_params;
+
+typedef struct vfp_batch vfp_batch;   /* a set of independent simulations      */
+typedef struct vfp_batch vfp_sim;     /* a single simulation: a set of one     */
+
+/* Defaults: n = 256, [-8, 8]^2, 1000 steps per period, beta = 1e-3, K = 4,
+ * no clamp, renormalize = 1, VFP_FP32, padding = 2, standard rotation,
+ * zero current, Gaussian start, max_steps = 0. */
+void vfp_params_init(vfp_params *p);
+
+/* sizeof(vfp_params) as compiled into the library (binding layout check). */
+size_t vfp_params_sizeof(void);
+
+/* Device bytes a workspace must hold for `count` simulations described by
+ * p[0..count-1].  Returns VFP_EINVAL for invalid parameters. */
+int vfp_workspace_size(const vfp_params *p, int32_t count, size_t *bytes);
+
+/* ---------------------------------------------------------------------- */
+/* Plain per-simulation form: one simulation, launched on its own.          */
+/* ---------------------------------------------------------------------- */
+
+/* Validates p (see vfp_params; also the explicit-Euler bound
+ * beta*dtheta/dp^2 <= 0.25, else VFP_EUNSTABLE), builds the wake table
+ * from Z on the device and uploads psi0.  Q0 = dq*dp*sum(psi0). */
+int vfp_create(const vfp_params *p, void *hip_stream, void *workspace, size_t ws_bytes,
+               vfp_sim **out);
+
+/* Enqueue nsteps >= 0 steps on the stream; no host synchronisation. */
+int vfp_step(vfp_sim *sim, int64_t nsteps);
+
+/* rho[0..n-1] = dp * sum_j psi_ij of the current (renormalised) state. */
+int vfp_profile(vfp_sim *sim, double *rho);
+
+/* CSR power of the current state (Sec. IV.C): *power = sum_i rho_i V_i,
+ * equal by Parseval to (S/M) sum_k Re Z_k |rho~_k|^2 over all M bins.  The
+ * FP64 wake is used for this diagnostic in every precision mode. */
+int vfp_csr_power(vfp_sim *sim, double *power);
+
+/* out = {Q, <q>, sigma_q, <p>, sigma_p} of the current state (FP64). */
+int vfp_moments(vfp_sim *sim, double out[5]);
+
+/* Copy the current state out (n*n FP64) / replace it (resets Q0 to the
+ * charge of the new psi and the step counter to 0). */
+int vfp_get_psi(vfp_sim *sim, double *psi);
+int vfp_set_psi(vfp_sim *sim, const double *psi);
+
+/* Time series (the paper's `outstep` output): after every `every`-th step a
+ * row {step, Q, <q>, sigma_q, <p>, sigma_p, P} of the state after that
+ * step is written on the device, up to `cap` rows (every = 0 stops).
+ * vfp_read_record copies rows*7 doubles into out (out may be NULL to only
+ * query *rows). */
+int vfp_record(vfp_sim *sim, int32_t every, int64_t cap);
+int vfp_read_record(vfp_sim *sim, double *out, int64_t *rows);
+
+/* Steps taken since create / the last set_psi. */
+int vfp_steps_done(vfp_sim *sim, int64_t *steps);
+
+void vfp_destroy(vfp_sim *sim);
+const char *vfp_last_error(void);
+
+/* ---------------------------------------------------------------------- */
+/* Batched form: `count` independent simulations (a current or shielding   */
+/* scan; grid sizes and steps per period may differ) advanced together.    */
+/* One tick advances every active simulation by one of its own steps with  */
+/* one fused launch (two in the mixed modes: the matrix-core wake first),  */
+/* replayed from a captured hipGraph.  All simulations of a batch share    */
+/* interp, clamp, precision and rotation.                                  */
+/* ---------------------------------------------------------------------- */
+int vfp_batch_create(const vfp_params *p, int32_t count, void *hip_stream, void *workspace,
+                     size_t ws_bytes, vfp_batch **out);
+int vfp_batch_step(vfp_batch *b, int64_t nticks);
+int vfp_batch_profile(vfp_batch *b, int32_t i, double *rho);
+int vfp_batch_csr_power(vfp_batch *b, double *power /* count */);
+int vfp_batch_moments(vfp_batch *b, double *out /* 5*count */);
+int vfp_batch_get_psi(vfp_batch *b, int32_t i, double *psi);
+int vfp_batch_set_psi(vfp_batch *b, int32_t i, const double *psi);
+int vfp_batch_record(vfp_batch *b, int32_t every, int64_t cap);
+int vfp_batch_read_record(vfp_batch *b, int32_t i, double *out, int64_t *rows);
+int vfp_batch_steps_done(vfp_batch *b, int32_t i, int64_t *steps);
+void vfp_batch_destroy(vfp_batch *b);
+
+/* Launch tuning: columns per work unit are chosen per grid size.  cells is
+ * the number of phase-space cells one workgroup owns (0 restores the
+ * built-in choice); use_graph = 0 launches every tick directly. */
+int vfp_batch_set_tuning(vfp_batch *b, int32_t cells_per_unit, int32_t use_graph);
+
+/* Autotuner: times `ticks` ticks for each candidate tile size with HIP
+ * events on the batch's stream, keeps the fastest, and returns the chosen
+ * cells per unit.  The state is saved and restored around the trials. */
+int vfp_batch_autotune(vfp_batch *b, int32_t ticks, int32_t *chosen_cells);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* VFP_H */

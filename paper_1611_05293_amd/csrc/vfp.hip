@@ -1,0 +1,1045 @@
+// vfp.hip -- host engine and C ABI of libvfp.so (see include/vfp.h).
+//
+// A handle owns a set of simulations (one for the plain form).  Device
+// memory is one arena (caller workspace or hipMalloc) carved per
+// simulation; work is described by "units" (a simulation and a strip of
+// whole q-columns) and one tick is one launch of the fused step kernel over
+// all units of the active simulations (preceded, in the mixed modes, by the
+// matrix-core wake).  Ticks are replayed from a captured hipGraph in the
+// batched form.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "vfp.h"
+#include "vfp_kernels.hpp"
+
+using namespace vfp;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const std::string &msg)
+{
+    g_err = msg;
+    return code;
+}
+
+#define HIPCHK(expr)                                                                          \
+    do {                                                                                      \
+        hipError_t e_ = (expr);                                                               \
+        if (e_ != hipSuccess)                                                                 \
+            return fail(VFP_EDEVICE, std::string(#expr) + ": " + hipGetErrorString(e_));      \
+    } while (0)
+
+constexpr size_t kAlign = 256;
+
+// Raise a kernel's dynamic-LDS limit when a launch needs more than before.
+template <typename K>
+void lds_limit(K kernel, size_t bytes, int &cur)
+{
+    if ((int)bytes > cur) {
+        if (hipFuncSetAttribute((const void *)kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes) ==
+            hipSuccess)
+            cur = (int)bytes;
+    }
+}
+size_t align_up(size_t x) { return (x + kAlign - 1) & ~(kAlign - 1); }
+
+struct HostSim {
+    vfp_params p{};
+    std::vector<double> zr, zi;
+    int64_t steps = 0;       // steps since create / set_psi
+    bool active = true;
+    int frozen_buf = 0;      // buffer holding the state once retired
+    // arena offsets
+    size_t off_psi[2], off_cs[2], off_wl64, off_wl32, off_frag, off_vext, off_sext, off_rho,
+        off_v, off_stat;
+    int nb = 0;
+};
+
+int choose_strip(int n, int cells)
+{
+    int w = cells / n;
+    w = std::max(1, std::min(w, std::min(n, kMaxStrip)));
+    return w;
+}
+
+int validate(const vfp_params &p, std::string &why)
+{
+    if (p.n < 16 || p.n > 4096) { why = "n must be in [16, 4096]"; return VFP_EINVAL; }
+    if (!(p.q_max > p.q_min) || !(p.p_max > p.p_min) || !std::isfinite(p.q_min) ||
+        !std::isfinite(p.q_max) || !std::isfinite(p.p_min) || !std::isfinite(p.p_max)) {
+        why = "need finite q_min < q_max and p_min < p_max";
+        return VFP_EINVAL;
+    }
+    if (p.steps_per_period < 1) { why = "steps_per_period must be >= 1"; return VFP_EINVAL; }
+    if (!(p.beta >= 0.0) || !std::isfinite(p.beta)) { why = "beta must be finite and >= 0"; return VFP_EINVAL; }
+    if (p.interp != 3 && p.interp != 4) { why = "interp must be 3 or 4"; return VFP_EINVAL; }
+    if (p.clamp != 0 && p.clamp != 1) { why = "clamp must be 0 or 1"; return VFP_EINVAL; }
+    if (p.renormalize != 0 && p.renormalize != 1) { why = "renormalize must be 0 or 1"; return VFP_EINVAL; }
+    if (p.precision < VFP_FP64 || p.precision > VFP_MIXED_FP16) { why = "unknown precision"; return VFP_EINVAL; }
+    if (p.padding < 2 || (int64_t)p.padding * p.n > (1 << 24)) { why = "padding must be >= 2"; return VFP_EINVAL; }
+    if (p.rotation != VFP_ROT_STANDARD && p.rotation != VFP_ROT_MANHATTAN) { why = "unknown rotation"; return VFP_EINVAL; }
+    if ((p.z_re == nullptr) != (p.z_im == nullptr)) { why = "z_re and z_im must both be set or both NULL"; return VFP_EINVAL; }
+    if (!std::isfinite(p.z_scale)) { why = "z_scale must be finite"; return VFP_EINVAL; }
+    if (p.max_steps < 0) { why = "max_steps must be >= 0"; return VFP_EINVAL; }
+    const double dp = (p.p_max - p.p_min) / (p.n - 1);
+    const double th = 2.0 * M_PI / p.steps_per_period;
+    if (p.beta * th / (dp * dp) > 0.25) {
+        why = "explicit damping/diffusion step unstable: beta*dtheta/dp^2 > 0.25";
+        return VFP_EUNSTABLE;
+    }
+    if (p.z_re) {
+        const int M = p.padding * p.n;
+        for (int k = 0; k <= M / 2; ++k)
+            if (!std::isfinite(p.z_re[k]) || !std::isfinite(p.z_im[k])) {
+                why = "impedance samples must be finite";
+                return VFP_EINVAL;
+            }
+    }
+    if (p.psi0) {
+        const size_t nn = (size_t)p.n * p.n;
+        for (size_t z = 0; z < nn; ++z)
+            if (!std::isfinite(p.psi0[z])) { why = "psi0 must be finite"; return VFP_EINVAL; }
+    }
+    return VFP_OK;
+}
+
+size_t elem_size(int precision) { return precision == VFP_FP64 ? 8 : 4; }
+
+// arena layout for count simulations; fills offsets when hs != nullptr
+size_t layout(const vfp_params *p, int count, std::vector<HostSim> *hs)
+{
+    size_t off = 0;
+    for (int s = 0; s < count; ++s) {
+        const vfp_params &q = p[s];
+        const size_t n = q.n, es = elem_size(q.precision);
+        const int nb = (q.n + 15) / 16;
+        HostSim tmp;
+        HostSim &h = hs ? (*hs)[s] : tmp;
+        h.nb = nb;
+        for (int b = 0; b < 2; ++b) { h.off_psi[b] = off; off = align_up(off + n * n * es); }
+        for (int b = 0; b < 2; ++b) { h.off_cs[b] = off; off = align_up(off + n * 8); }
+        h.off_wl64 = off; off = align_up(off + (2 * n - 1) * 8);
+        h.off_wl32 = off; off = align_up(off + (2 * n - 1) * 4);
+        h.off_frag = off;
+        if (q.precision >= VFP_MIXED_BF16) off = align_up(off + (size_t)(2 * nb - 1) * 256 * 4);
+        h.off_vext = off; off = align_up(off + n * 4);
+        h.off_sext = off; off = align_up(off + 2 * 8);
+        h.off_rho = off; off = align_up(off + n * 8);
+        h.off_v = off; off = align_up(off + n * 8);
+        h.off_stat = off; off = align_up(off + 8 * 8);
+    }
+    return off;
+}
+
+}  // namespace
+
+struct vfp_batch {
+    int count = 0;
+    int precision = VFP_FP32, K = 4, clamp = 0, rotation = 0;
+    bool plain = false;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    std::vector<HostSim> hs;
+    std::vector<SimDev> sd;
+    SimDev *d_sd = nullptr;
+    unsigned char *arena = nullptr;
+    size_t arena_bytes = 0;
+    bool own_arena = false;
+    // units of the active simulations
+    int cells = 0;
+    std::vector<Unit> units;
+    Unit *d_units = nullptr;
+    size_t units_cap = 0;
+    std::vector<int> active;       // active simulation indices
+    int *d_active = nullptr;       // device copy of `active`
+    int *d_idx = nullptr;          // scratch index arrays for per-call kernels (2*count)
+    int *d_buf01 = nullptr;        // count zeros then count ones: buffer tables for records
+    bool units_dirty = true;
+    int64_t tick = 0;              // ticks since create
+    int parity = 0;                // buffer holding the state of active simulations
+    // graph
+    bool use_graph = true;
+    hipGraphExec_t gexec = nullptr;
+    hipGraph_t graph = nullptr;
+    int graph_ticks = 0, graph_parity = -1;
+    int64_t graph_phase = -1;
+    bool graph_valid = false;
+    // record
+    int every = 0;
+    int64_t rec_cap = 0, rec_base = 0;
+    double *d_ring = nullptr;
+    int64_t *d_ring_rows = nullptr;
+    // staging for psi transfers and impedance uploads
+    double *d_stage = nullptr;
+    size_t stage_elems = 0;
+    size_t lds_step = 0, lds_stats = 0, lds_wake = 0;
+};
+
+namespace {
+
+int ensure_stage(vfp_batch *b, size_t elems)
+{
+    if (b->stage_elems >= elems) return VFP_OK;
+    if (b->d_stage) HIPCHK(hipFree(b->d_stage));
+    b->d_stage = nullptr;
+    b->stage_elems = 0;
+    HIPCHK(hipMalloc(&b->d_stage, elems * sizeof(double)));
+    b->stage_elems = elems;
+    return VFP_OK;
+}
+
+// host -> device copy that has completed when it returns (sources are often
+// short-lived host vectors)
+int upload(void *dst, const void *src, size_t bytes, hipStream_t st)
+{
+    HIPCHK(hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, st));
+    HIPCHK(hipStreamSynchronize(st));
+    return VFP_OK;
+}
+
+int upload_sims(vfp_batch *b) { return upload(b->d_sd, b->sd.data(), sizeof(SimDev) * b->count, b->stream); }
+
+int rebuild_units(vfp_batch *b)
+{
+    b->active.clear();
+    for (int s = 0; s < b->count; ++s)
+        if (b->hs[s].active) b->active.push_back(s);
+    b->units.clear();
+    for (int s : b->active) {
+        const int n = b->hs[s].p.n;
+        const int w = choose_strip(n, b->cells);
+        for (int i0 = 0; i0 < n; i0 += w) b->units.push_back(Unit{s, i0, std::min(w, n - i0), 0});
+    }
+    if (b->units.size() > b->units_cap) {
+        if (b->d_units) HIPCHK(hipFree(b->d_units));
+        b->d_units = nullptr;
+        HIPCHK(hipMalloc(&b->d_units, sizeof(Unit) * b->units.size()));
+        b->units_cap = b->units.size();
+    }
+    int rc = VFP_OK;
+    if (!b->units.empty()) rc = upload(b->d_units, b->units.data(), sizeof(Unit) * b->units.size(), b->stream);
+    if (rc) return rc;
+    if (!b->active.empty()) rc = upload(b->d_active, b->active.data(), sizeof(int) * b->active.size(), b->stream);
+    if (rc) return rc;
+    // LDS of the fused step: two strip buffers
+    size_t mx = 0;
+    for (const Unit &u : b->units) mx = std::max(mx, (size_t)u.w * b->hs[u.sim].p.n);
+    b->lds_step = 2 * mx * elem_size(b->precision);
+    if (b->lds_step > 64 * 1024 + 64 * 1024)
+        return fail(VFP_EINVAL, "strip does not fit the workgroup's LDS; lower cells_per_unit");
+    b->units_dirty = false;
+    b->graph_valid = false;
+    return VFP_OK;
+}
+
+// ------------------------------------------------------------- launches
+template <typename T, int K, int WAKE, bool CL, int ROT>
+void launch_step_t(vfp_batch *b, int parity)
+{
+    auto k = step_kernel<T, K, WAKE, CL, ROT>;
+    static int cur = 0;
+    lds_limit(k, b->lds_step, cur);
+    hipLaunchKernelGGL(k, dim3((unsigned)b->units.size()), dim3(kThreads), b->lds_step, b->stream,
+                       b->d_sd, b->d_units, (int)b->units.size(), parity);
+}
+
+template <typename T, int K, int WAKE>
+void launch_step_w(vfp_batch *b, int parity)
+{
+    if (b->clamp) {
+        if (b->rotation) launch_step_t<T, K, WAKE, true, 1>(b, parity);
+        else launch_step_t<T, K, WAKE, true, 0>(b, parity);
+    } else {
+        if (b->rotation) launch_step_t<T, K, WAKE, false, 1>(b, parity);
+        else launch_step_t<T, K, WAKE, false, 0>(b, parity);
+    }
+}
+
+template <typename T, int WAKE>
+void launch_step_k(vfp_batch *b, int parity)
+{
+    if (b->K == 3) launch_step_w<T, 3, WAKE>(b, parity);
+    else launch_step_w<T, 4, WAKE>(b, parity);
+}
+
+bool any_wake(const vfp_batch *b)
+{
+    for (int s : b->active)
+        if (b->sd[s].has_wake) return true;
+    return false;
+}
+
+int launch_tick(vfp_batch *b, int parity)
+{
+    if (b->units.empty()) return VFP_OK;
+    const bool wake = any_wake(b);
+    if (b->precision == VFP_FP64) {
+        if (wake) launch_step_k<double, WAKE_FUSED>(b, parity);
+        else launch_step_k<double, WAKE_NONE>(b, parity);
+    } else if (b->precision == VFP_FP32 || !wake) {
+        if (wake) launch_step_k<float, WAKE_FUSED>(b, parity);
+        else launch_step_k<float, WAKE_NONE>(b, parity);
+    } else {
+        const bool fp16 = b->precision == VFP_MIXED_FP16;
+        auto wk = fp16 ? wake_mfma_kernel<true> : wake_mfma_kernel<false>;
+        static int cur16 = 0, cur8 = 0;
+        lds_limit(wk, b->lds_wake, fp16 ? cur16 : cur8);
+        hipLaunchKernelGGL(wk, dim3((unsigned)b->active.size()), dim3(kThreads), b->lds_wake, b->stream,
+                           b->d_sd, b->d_active, parity);
+        launch_step_k<float, WAKE_EXTERNAL>(b, parity);
+    }
+    HIPCHK(hipGetLastError());
+    return VFP_OK;
+}
+
+// stats over an explicit list of (simulation, buffer) pairs
+int launch_stats(vfp_batch *b, const int *d_which, const int *d_buf, int cnt, int record)
+{
+    if (cnt == 0) return VFP_OK;
+    if (b->precision == VFP_FP64) {
+        static int cur = 0;
+        lds_limit(stats_kernel<double>, b->lds_stats, cur);
+        hipLaunchKernelGGL(stats_kernel<double>, dim3(cnt), dim3(kThreads), b->lds_stats, b->stream, b->d_sd,
+                           d_which, d_buf, b->rec_base, b->every, record);
+    } else {
+        static int cur = 0;
+        lds_limit(stats_kernel<float>, b->lds_stats, cur);
+        hipLaunchKernelGGL(stats_kernel<float>, dim3(cnt), dim3(kThreads), b->lds_stats, b->stream, b->d_sd,
+                           d_which, d_buf, b->rec_base, b->every, record);
+    }
+    HIPCHK(hipGetLastError());
+    return VFP_OK;
+}
+
+// record launch after a tick that read buffer `par`: every active simulation's
+// fresh state is in buffer par ^ 1
+int launch_record(vfp_batch *b, int par)
+{
+    return launch_stats(b, b->d_active, b->d_buf01 + (par ^ 1) * b->count, (int)b->active.size(), 1);
+}
+
+// d_idx[0..count) = all simulations, d_idx[count..2count) = their buffers
+int stage_all_indices(vfp_batch *b)
+{
+    std::vector<int> v(2 * b->count);
+    for (int s = 0; s < b->count; ++s) {
+        v[s] = s;
+        v[b->count + s] = b->hs[s].active ? b->parity : b->hs[s].frozen_buf;
+    }
+    return upload(b->d_idx, v.data(), sizeof(int) * v.size(), b->stream);
+}
+
+int refresh_stats(vfp_batch *b)
+{
+    int rc = stage_all_indices(b);
+    if (rc) return rc;
+    rc = launch_stats(b, b->d_idx, b->d_idx + b->count, b->count, 0);
+    if (rc) return rc;
+    HIPCHK(hipStreamSynchronize(b->stream));
+    return VFP_OK;
+}
+
+int check_finite(vfp_batch *b, int s)
+{
+    double bad = 0.0;
+    HIPCHK(hipMemcpy(&bad, (double *)(b->arena + b->hs[s].off_stat) + 7, sizeof(double), hipMemcpyDeviceToHost));
+    if (bad != 0.0) return fail(VFP_EDEVICE, "non-finite density or wake detected");
+    return VFP_OK;
+}
+
+// one direct tick (plus the record launch when due)
+int direct_tick(vfp_batch *b)
+{
+    int rc = launch_tick(b, b->parity);
+    if (rc) return rc;
+    if (b->every > 0 && ((b->tick + 1 - b->rec_base) % b->every) == 0) rc = launch_record(b, b->parity);
+    return rc;
+}
+
+// capture G ticks starting at the current tick and parity
+int capture_graph(vfp_batch *b, int G)
+{
+    if (b->gexec) { (void)hipGraphExecDestroy(b->gexec); b->gexec = nullptr; }
+    if (b->graph) { (void)hipGraphDestroy(b->graph); b->graph = nullptr; }
+    HIPCHK(hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
+    int par = b->parity;
+    int rc = VFP_OK;
+    for (int t = 0; t < G && rc == VFP_OK; ++t) {
+        rc = launch_tick(b, par);
+        if (rc == VFP_OK && b->every > 0 && ((b->tick + t + 1 - b->rec_base) % b->every) == 0)
+            rc = launch_record(b, par);
+        par ^= 1;
+    }
+    hipGraph_t g = nullptr;
+    const hipError_t e = hipStreamEndCapture(b->stream, &g);
+    if (rc) { if (g) (void)hipGraphDestroy(g); return rc; }
+    if (e != hipSuccess) return fail(VFP_EDEVICE, std::string("graph capture: ") + hipGetErrorString(e));
+    b->graph = g;
+    HIPCHK(hipGraphInstantiate(&b->gexec, g, nullptr, nullptr, 0));
+    b->graph_ticks = G;
+    b->graph_parity = b->parity;
+    b->graph_valid = true;
+    return VFP_OK;
+}
+
+int advance(vfp_batch *b, int64_t nticks)
+{
+    if (nticks < 0) return fail(VFP_EINVAL, "negative step count");
+    int rc;
+    // graph length: even (keeps the parity) and a multiple of the record cadence
+    int G = 0;
+    if (b->use_graph) {
+        G = b->every > 0 ? (b->every % 2 ? 2 * b->every : b->every) : 16;
+        while (G < 16) G *= 2;
+    }
+    while (nticks > 0) {
+        if (b->units_dirty) {
+            rc = rebuild_units(b);
+            if (rc) return rc;
+        }
+        if (b->active.empty()) return VFP_OK;
+        // ticks until the next retirement
+        int64_t until = nticks;
+        for (int s : b->active) {
+            const int64_t ms = b->hs[s].p.max_steps;
+            if (ms > 0) until = std::min(until, ms - b->hs[s].steps);
+        }
+        if (until <= 0) {
+            for (int s : b->active)
+                if (b->hs[s].p.max_steps > 0 && b->hs[s].steps >= b->hs[s].p.max_steps) {
+                    b->hs[s].active = false;
+                    b->hs[s].frozen_buf = b->parity;
+                }
+            b->units_dirty = true;
+            continue;
+        }
+        int64_t done = 0;
+        while (done < until) {
+            const int64_t left = until - done;
+            const bool aligned = b->every == 0 || ((b->tick - b->rec_base) % b->every) == 0;
+            if (G > 0 && left >= G && aligned) {
+                if (!b->graph_valid || b->graph_ticks != G || b->graph_parity != b->parity) {
+                    rc = capture_graph(b, G);
+                    if (rc) return rc;
+                }
+                HIPCHK(hipGraphLaunch(b->gexec, b->stream));
+                b->tick += G;
+                done += G;
+            } else {
+                rc = direct_tick(b);
+                if (rc) return rc;
+                b->parity ^= 1;
+                ++b->tick;
+                ++done;
+            }
+        }
+        for (int s : b->active) b->hs[s].steps += done;
+        nticks -= done;
+    }
+    return VFP_OK;
+}
+
+void free_batch(vfp_batch *b)
+{
+    if (!b) return;
+    if (b->stream) (void)hipStreamSynchronize(b->stream);
+    if (b->gexec) (void)hipGraphExecDestroy(b->gexec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    if (b->own_arena && b->arena) (void)hipFree(b->arena);
+    if (b->d_sd) (void)hipFree(b->d_sd);
+    if (b->d_units) (void)hipFree(b->d_units);
+    if (b->d_active) (void)hipFree(b->d_active);
+    if (b->d_idx) (void)hipFree(b->d_idx);
+    if (b->d_buf01) (void)hipFree(b->d_buf01);
+    if (b->d_ring) (void)hipFree(b->d_ring);
+    if (b->d_ring_rows) (void)hipFree(b->d_ring_rows);
+    if (b->d_stage) (void)hipFree(b->d_stage);
+    if (b->own_stream) (void)hipStreamDestroy(b->stream);
+    delete b;
+}
+
+int upload_psi(vfp_batch *b, int s, const double *psi, bool gaussian)
+{
+    const HostSim &h = b->hs[s];
+    const int n = h.p.n;
+    const size_t nn = (size_t)n * n;
+    std::vector<double> g;
+    if (gaussian) {
+        // unit Gaussian on the node grid, normalised to unit charge (input data)
+        g.resize(nn);
+        const double dq = (h.p.q_max - h.p.q_min) / (n - 1), dp = (h.p.p_max - h.p.p_min) / (n - 1);
+        double sum = 0.0;
+        for (int i = 0; i < n; ++i)
+            for (int j = 0; j < n; ++j) {
+                const double q = h.p.q_min + i * dq, p = h.p.p_min + j * dp;
+                g[(size_t)i * n + j] = std::exp(-0.5 * (q * q + p * p));
+                sum += g[(size_t)i * n + j];
+            }
+        for (double &v : g) v /= sum * dq * dp;
+        psi = g.data();
+    }
+    int rc = ensure_stage(b, nn);
+    if (rc) return rc;
+    rc = upload(b->d_stage, psi, nn * sizeof(double), b->stream);
+    if (rc) return rc;
+    const int buf = h.active ? b->parity : h.frozen_buf;
+    void *dst = b->arena + h.off_psi[buf];
+    const unsigned blocks = (unsigned)((nn + kThreads - 1) / kThreads);
+    if (b->precision == VFP_FP64)
+        hipLaunchKernelGGL(import_kernel<double>, dim3(blocks), dim3(kThreads), 0, b->stream, b->d_stage,
+                           (double *)dst, nn);
+    else
+        hipLaunchKernelGGL(import_kernel<float>, dim3(blocks), dim3(kThreads), 0, b->stream, b->d_stage,
+                           (float *)dst, nn);
+    HIPCHK(hipGetLastError());
+    // column sums of the new state, then Q0 = dq*dp*sum from the device
+    const int v[2] = {s, buf};
+    rc = upload(b->d_idx, v, sizeof(v), b->stream);
+    if (rc) return rc;
+    const unsigned cb = (unsigned)((n + kWaves - 1) / kWaves);
+    if (b->precision == VFP_FP64)
+        hipLaunchKernelGGL(project_kernel<double>, dim3(cb, 1), dim3(kThreads), 0, b->stream, b->d_sd, b->d_idx, buf);
+    else
+        hipLaunchKernelGGL(project_kernel<float>, dim3(cb, 1), dim3(kThreads), 0, b->stream, b->d_sd, b->d_idx, buf);
+    HIPCHK(hipGetLastError());
+    // Q0 from the stats kernel with renormalisation off: stat[0] = dq*dp*sum(psi)
+    const int renorm = b->sd[s].renorm;
+    b->sd[s].renorm = 0;
+    rc = upload_sims(b);
+    if (rc) return rc;
+    rc = launch_stats(b, b->d_idx, b->d_idx + 1, 1, 0);
+    if (rc) return rc;
+    double Q0 = 0.0;
+    HIPCHK(hipMemcpyAsync(&Q0, b->arena + h.off_stat, sizeof(double), hipMemcpyDeviceToHost, b->stream));
+    HIPCHK(hipStreamSynchronize(b->stream));
+    if (!(Q0 > 0.0) || !std::isfinite(Q0)) {
+        b->sd[s].renorm = renorm;
+        upload_sims(b);
+        return fail(VFP_EINVAL, "initial density must have a positive, finite charge");
+    }
+    b->sd[s].renorm = renorm;
+    b->sd[s].Q0 = Q0;
+    b->sd[s].step0 = b->tick;
+    rc = upload_sims(b);
+    if (rc) return rc;
+    b->graph_valid = false;
+    return VFP_OK;
+}
+
+int create_impl(const vfp_params *p, int32_t count, void *stream, void *ws, size_t ws_bytes, bool plain,
+                vfp_batch **out)
+{
+    if (!out) return fail(VFP_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!p || count < 1) return fail(VFP_EINVAL, "need at least one parameter set");
+    std::string why;
+    for (int s = 0; s < count; ++s) {
+        const int rc = validate(p[s], why);
+        if (rc) return fail(rc, "simulation " + std::to_string(s) + ": " + why);
+        if (p[s].interp != p[0].interp || p[s].clamp != p[0].clamp || p[s].precision != p[0].precision ||
+            p[s].rotation != p[0].rotation)
+            return fail(VFP_EINVAL, "interp, clamp, precision and rotation must agree across a batch");
+    }
+    vfp_batch *b = new vfp_batch();
+    b->count = count;
+    b->plain = plain;
+    b->use_graph = !plain;
+    b->precision = p[0].precision;
+    b->K = p[0].interp;
+    b->clamp = p[0].clamp;
+    b->rotation = p[0].rotation;
+    b->cells = b->precision == VFP_FP64 ? 4096 : 8192;
+    b->stream = (hipStream_t)stream;
+    if (!b->stream) {
+        // graphs cannot be captured on the null stream: use a stream of our own
+        if (hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking) != hipSuccess) {
+            delete b;
+            return fail(VFP_EDEVICE, "stream creation failed");
+        }
+        b->own_stream = true;
+    }
+    b->hs.resize(count);
+    for (int s = 0; s < count; ++s) {
+        HostSim &h = b->hs[s];
+        h.p = p[s];
+        if (p[s].z_re) {
+            const int M = p[s].padding * p[s].n;
+            h.zr.assign(p[s].z_re, p[s].z_re + M / 2 + 1);
+            h.zi.assign(p[s].z_im, p[s].z_im + M / 2 + 1);
+        }
+        h.p.z_re = h.p.z_im = nullptr;
+        h.p.psi0 = nullptr;
+    }
+    const size_t need = layout(p, count, &b->hs);
+    if (ws) {
+        if (ws_bytes < need) {
+            free_batch(b);
+            return fail(VFP_ENOMEM, "workspace too small: need " + std::to_string(need) + " bytes");
+        }
+        b->arena = (unsigned char *)ws;
+    } else {
+        if (hipMalloc(&b->arena, need) != hipSuccess) {
+            free_batch(b);
+            return fail(VFP_ENOMEM, "device allocation of " + std::to_string(need) + " bytes failed");
+        }
+        b->own_arena = true;
+    }
+    b->arena_bytes = need;
+    int rc = VFP_OK;
+    auto bail = [&](int code) { free_batch(b); return code; };
+    if (hipMalloc(&b->d_sd, sizeof(SimDev) * count) != hipSuccess ||
+        hipMalloc(&b->d_active, sizeof(int) * count) != hipSuccess ||
+        hipMalloc(&b->d_idx, sizeof(int) * 2 * count) != hipSuccess ||
+        hipMalloc(&b->d_buf01, sizeof(int) * 2 * count) != hipSuccess)
+        return bail(fail(VFP_ENOMEM, "device allocation failed"));
+    {
+        std::vector<int> t01(2 * count, 0);
+        for (int s = 0; s < count; ++s) t01[count + s] = 1;
+        if (hipMemcpy(b->d_buf01, t01.data(), sizeof(int) * t01.size(), hipMemcpyHostToDevice) != hipSuccess)
+            return bail(fail(VFP_EDEVICE, "upload failed"));
+    }
+    // descriptors
+    b->sd.resize(count);
+    int maxn = 0;
+    for (int s = 0; s < count; ++s) {
+        const HostSim &h = b->hs[s];
+        const vfp_params &q = h.p;
+        SimDev &d = b->sd[s];
+        std::memset(&d, 0, sizeof(d));
+        maxn = std::max(maxn, q.n);
+        d.n = q.n;
+        d.K = q.interp;
+        d.rotation = q.rotation;
+        d.clamp = q.clamp;
+        d.renorm = q.renormalize;
+        d.has_wake = p[s].z_re != nullptr ? 1 : 0;
+        d.M = q.padding * q.n;
+        d.q_min = q.q_min;
+        d.p_min = q.p_min;
+        d.dq = (q.q_max - q.q_min) / (q.n - 1);
+        d.dp = (q.p_max - q.p_min) / (q.n - 1);
+        d.th = 2.0 * M_PI / q.steps_per_period;
+        d.c = std::cos(d.th);
+        d.s = std::sin(d.th);
+        d.bt = q.beta * d.th;
+        d.kick = d.th / d.dp;
+        d.S = q.z_scale;
+        d.Q0 = 1.0;
+        const double cm1 = -2.0 * std::sin(0.5 * d.th) * std::sin(0.5 * d.th);   // cos - 1
+        d.ax0 = (q.q_min * cm1 - q.p_min * d.s) / d.dq;
+        d.axi = cm1;
+        d.bx = -d.s * d.dp / d.dq;
+        d.cy0 = (q.q_min * d.s + q.p_min * cm1) / d.dp;
+        d.cyi = d.s * d.dq / d.dp;
+        d.by = cm1;
+        d.pm = q.p_min / d.dp;
+        d.tw = d.th * d.dp / d.dq;
+        d.tk = d.th * d.dq / d.dp;
+        unsigned char *A = b->arena;
+        d.psi[0] = A + h.off_psi[0];
+        d.psi[1] = A + h.off_psi[1];
+        d.colsum[0] = (double *)(A + h.off_cs[0]);
+        d.colsum[1] = (double *)(A + h.off_cs[1]);
+        d.wl64 = (const double *)(A + h.off_wl64);
+        d.wl32 = (const float *)(A + h.off_wl32);
+        d.afrag = (const uint32_t *)(A + h.off_frag);
+        d.vext = (float *)(A + h.off_vext);
+        d.sext = (double *)(A + h.off_sext);
+        d.rho_out = (double *)(A + h.off_rho);
+        d.v_out = (double *)(A + h.off_v);
+        d.stat = (double *)(A + h.off_stat);
+    }
+    b->lds_stats = 2 * (size_t)maxn * sizeof(double);
+    b->lds_wake = 2 * 16 * (size_t)(((maxn + 15) / 16) + 30) * sizeof(uint16_t);
+    HIPCHK(hipMemsetAsync(b->arena, 0, need, b->stream));
+    rc = upload_sims(b);
+    if (rc) return bail(rc);
+    // wake tables from the impedance samples
+    for (int s = 0; s < count; ++s) {
+        const HostSim &h = b->hs[s];
+        if (!b->sd[s].has_wake) continue;
+        const int n = h.p.n, M = b->sd[s].M, nz = M / 2 + 1;
+        rc = ensure_stage(b, 2 * (size_t)nz);
+        if (rc) return bail(rc);
+        if (upload(b->d_stage, h.zr.data(), nz * sizeof(double), b->stream) ||
+            upload(b->d_stage + nz, h.zi.data(), nz * sizeof(double), b->stream))
+            return bail(fail(VFP_EDEVICE, "impedance upload failed"));
+        hipLaunchKernelGGL(wake_table_kernel, dim3((2 * n - 1 + kThreads - 1) / kThreads), dim3(kThreads), 0,
+                           b->stream, n, M, b->d_stage, b->d_stage + nz, (double *)(b->arena + h.off_wl64),
+                           (float *)(b->arena + h.off_wl32));
+        if (b->precision >= VFP_MIXED_BF16) {
+            // power-of-two scale of the wake fragments from max |w| (device table read back)
+            std::vector<double> wl(2 * n - 1);
+            if (hipMemcpyAsync(wl.data(), b->arena + h.off_wl64, wl.size() * sizeof(double), hipMemcpyDeviceToHost,
+                               b->stream) ||
+                hipStreamSynchronize(b->stream))
+                return bail(fail(VFP_EDEVICE, "wake table readback failed"));
+            double mw = 0.0;
+            for (double v : wl) mw = std::max(mw, std::fabs(v));
+            int e = 0;
+            if (b->precision == VFP_MIXED_FP16 && mw > 0.0) {
+                std::frexp(mw, &e);
+                e = 14 - e;
+            }
+            const double wscale = std::ldexp(1.0, e), wback = std::ldexp(1.0, -e);
+            const int nb = h.nb;
+            const unsigned fb = (unsigned)(((2 * nb - 1) * 64 + kThreads - 1) / kThreads);
+            if (b->precision == VFP_MIXED_FP16)
+                hipLaunchKernelGGL(wake_frag_kernel<true>, dim3(fb), dim3(kThreads), 0, b->stream, n, nb,
+                                   (const double *)(b->arena + h.off_wl64), wscale, (uint32_t *)(b->arena + h.off_frag));
+            else
+                hipLaunchKernelGGL(wake_frag_kernel<false>, dim3(fb), dim3(kThreads), 0, b->stream, n, nb,
+                                   (const double *)(b->arena + h.off_wl64), wscale, (uint32_t *)(b->arena + h.off_frag));
+            const double sx[2] = {1.0, wback};
+            if (upload(b->arena + h.off_sext, sx, sizeof(sx), b->stream))
+                return bail(fail(VFP_EDEVICE, "fragment setup failed"));
+        }
+        if (hipGetLastError() != hipSuccess || hipStreamSynchronize(b->stream) != hipSuccess)
+            return bail(fail(VFP_EDEVICE, "wake table setup failed"));
+    }
+    for (int s = 0; s < count; ++s) {
+        rc = upload_psi(b, s, p[s].psi0, p[s].psi0 == nullptr);
+        if (rc) return bail(rc);
+    }
+    rc = rebuild_units(b);
+    if (rc) return bail(rc);
+    if (hipStreamSynchronize(b->stream) != hipSuccess) return bail(fail(VFP_EDEVICE, "setup failed"));
+    *out = b;
+    return VFP_OK;
+}
+
+const double *stat_ptr(vfp_batch *b, int s) { return (const double *)(b->arena + b->hs[s].off_stat); }
+
+int get_psi_impl(vfp_batch *b, int s, double *psi)
+{
+    if (!psi) return fail(VFP_EINVAL, "psi is NULL");
+    int rc = refresh_stats(b);
+    if (rc) return rc;
+    const HostSim &h = b->hs[s];
+    const size_t nn = (size_t)h.p.n * h.p.n;
+    rc = ensure_stage(b, nn);
+    if (rc) return rc;
+    const int buf = h.active ? b->parity : h.frozen_buf;
+    const unsigned blocks = (unsigned)((nn + kThreads - 1) / kThreads);
+    if (b->precision == VFP_FP64)
+        hipLaunchKernelGGL(export_kernel<double>, dim3(blocks), dim3(kThreads), 0, b->stream,
+                           (const double *)(b->arena + h.off_psi[buf]), stat_ptr(b, s), b->d_stage, nn);
+    else
+        hipLaunchKernelGGL(export_kernel<float>, dim3(blocks), dim3(kThreads), 0, b->stream,
+                           (const float *)(b->arena + h.off_psi[buf]), stat_ptr(b, s), b->d_stage, nn);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipMemcpyAsync(psi, b->d_stage, nn * sizeof(double), hipMemcpyDeviceToHost, b->stream));
+    HIPCHK(hipStreamSynchronize(b->stream));
+    return check_finite(b, s);
+}
+
+int record_impl(vfp_batch *b, int32_t every, int64_t cap)
+{
+    if (every < 0 || cap < 0) return fail(VFP_EINVAL, "every and cap must be >= 0");
+    HIPCHK(hipStreamSynchronize(b->stream));
+    if (b->d_ring) { HIPCHK(hipFree(b->d_ring)); b->d_ring = nullptr; }
+    if (b->d_ring_rows) { HIPCHK(hipFree(b->d_ring_rows)); b->d_ring_rows = nullptr; }
+    b->every = 0;
+    b->rec_cap = 0;
+    for (int s = 0; s < b->count; ++s) {
+        b->sd[s].ring = nullptr;
+        b->sd[s].ring_rows = nullptr;
+        b->sd[s].ring_cap = 0;
+    }
+    if (every > 0 && cap > 0) {
+        HIPCHK(hipMalloc(&b->d_ring, sizeof(double) * 7 * (size_t)cap * b->count));
+        HIPCHK(hipMalloc(&b->d_ring_rows, sizeof(int64_t) * b->count));
+        HIPCHK(hipMemsetAsync(b->d_ring_rows, 0, sizeof(int64_t) * b->count, b->stream));
+        for (int s = 0; s < b->count; ++s) {
+            b->sd[s].ring = b->d_ring + 7 * (size_t)cap * s;
+            b->sd[s].ring_rows = b->d_ring_rows + s;
+            b->sd[s].ring_cap = cap;
+        }
+        b->every = every;
+        b->rec_cap = cap;
+        b->rec_base = b->tick;
+    }
+    int rc = upload_sims(b);
+    if (rc) return rc;
+    b->graph_valid = false;
+    HIPCHK(hipStreamSynchronize(b->stream));
+    return VFP_OK;
+}
+
+int read_record_impl(vfp_batch *b, int s, double *out, int64_t *rows)
+{
+    if (!rows) return fail(VFP_EINVAL, "rows is NULL");
+    *rows = 0;
+    if (!b->d_ring) return VFP_OK;
+    HIPCHK(hipStreamSynchronize(b->stream));
+    int64_t r = 0;
+    HIPCHK(hipMemcpy(&r, b->d_ring_rows + s, sizeof(int64_t), hipMemcpyDeviceToHost));
+    r = std::min(r, b->rec_cap);
+    *rows = r;
+    if (out && r > 0)
+        HIPCHK(hipMemcpy(out, b->d_ring + 7 * (size_t)b->rec_cap * s, sizeof(double) * 7 * r, hipMemcpyDeviceToHost));
+    return VFP_OK;
+}
+
+}  // namespace
+
+// ====================================================================== ABI
+extern "C" {
+
+void vfp_params_init(vfp_params *p)
+{
+    if (!p) return;
+    std::memset(p, 0, sizeof(*p));
+    p->n = 256;
+    p->q_min = p->p_min = -8.0;
+    p->q_max = p->p_max = 8.0;
+    p->steps_per_period = 1000;
+    p->beta = 1e-3;
+    p->interp = 4;
+    p->clamp = 0;
+    p->renormalize = 1;
+    p->precision = VFP_FP32;
+    p->padding = 2;
+    p->rotation = VFP_ROT_STANDARD;
+    p->z_scale = 0.0;
+    p->max_steps = 0;
+}
+
+size_t vfp_params_sizeof(void) { return sizeof(vfp_params); }
+
+const char *vfp_last_error(void) { return g_err.c_str(); }
+
+int vfp_workspace_size(const vfp_params *p, int32_t count, size_t *bytes)
+{
+    if (!p || !bytes || count < 1) return fail(VFP_EINVAL, "invalid arguments");
+    std::string why;
+    for (int s = 0; s < count; ++s) {
+        const int rc = validate(p[s], why);
+        if (rc) return fail(rc, why);
+    }
+    *bytes = layout(p, count, nullptr);
+    return VFP_OK;
+}
+
+int vfp_create(const vfp_params *p, void *hip_stream, void *workspace, size_t ws_bytes, vfp_sim **out)
+{
+    return create_impl(p, 1, hip_stream, workspace, ws_bytes, true, out);
+}
+
+int vfp_batch_create(const vfp_params *p, int32_t count, void *hip_stream, void *workspace, size_t ws_bytes,
+                     vfp_batch **out)
+{
+    return create_impl(p, count, hip_stream, workspace, ws_bytes, false, out);
+}
+
+int vfp_step(vfp_sim *sim, int64_t nsteps)
+{
+    if (!sim) return fail(VFP_EINVAL, "NULL handle");
+    return advance(sim, nsteps);
+}
+
+int vfp_batch_step(vfp_batch *b, int64_t nticks)
+{
+    if (!b) return fail(VFP_EINVAL, "NULL handle");
+    return advance(b, nticks);
+}
+
+int vfp_batch_profile(vfp_batch *b, int32_t i, double *rho)
+{
+    if (!b || !rho || i < 0 || i >= b->count) return fail(VFP_EINVAL, "invalid arguments");
+    int rc = refresh_stats(b);
+    if (rc) return rc;
+    HIPCHK(hipMemcpy(rho, b->arena + b->hs[i].off_rho, sizeof(double) * b->hs[i].p.n, hipMemcpyDeviceToHost));
+    return check_finite(b, i);
+}
+
+int vfp_profile(vfp_sim *sim, double *rho) { return vfp_batch_profile(sim, 0, rho); }
+
+int vfp_batch_csr_power(vfp_batch *b, double *power)
+{
+    if (!b || !power) return fail(VFP_EINVAL, "invalid arguments");
+    int rc = refresh_stats(b);
+    if (rc) return rc;
+    for (int s = 0; s < b->count; ++s) {
+        HIPCHK(hipMemcpy(power + s, stat_ptr(b, s) + 5, sizeof(double), hipMemcpyDeviceToHost));
+        rc = check_finite(b, s);
+        if (rc) return rc;
+    }
+    return VFP_OK;
+}
+
+int vfp_csr_power(vfp_sim *sim, double *power) { return vfp_batch_csr_power(sim, power); }
+
+int vfp_batch_moments(vfp_batch *b, double *out)
+{
+    if (!b || !out) return fail(VFP_EINVAL, "invalid arguments");
+    int rc = refresh_stats(b);
+    if (rc) return rc;
+    for (int s = 0; s < b->count; ++s) {
+        HIPCHK(hipMemcpy(out + 5 * s, stat_ptr(b, s), 5 * sizeof(double), hipMemcpyDeviceToHost));
+        rc = check_finite(b, s);
+        if (rc) return rc;
+    }
+    return VFP_OK;
+}
+
+int vfp_moments(vfp_sim *sim, double out[5]) { return vfp_batch_moments(sim, out); }
+
+int vfp_batch_get_psi(vfp_batch *b, int32_t i, double *psi)
+{
+    if (!b || i < 0 || i >= b->count) return fail(VFP_EINVAL, "invalid arguments");
+    return get_psi_impl(b, i, psi);
+}
+
+int vfp_get_psi(vfp_sim *sim, double *psi) { return vfp_batch_get_psi(sim, 0, psi); }
+
+int vfp_batch_set_psi(vfp_batch *b, int32_t i, const double *psi)
+{
+    if (!b || !psi || i < 0 || i >= b->count) return fail(VFP_EINVAL, "invalid arguments");
+    const size_t nn = (size_t)b->hs[i].p.n * b->hs[i].p.n;
+    for (size_t z = 0; z < nn; ++z)
+        if (!std::isfinite(psi[z])) return fail(VFP_EINVAL, "psi must be finite");
+    HIPCHK(hipStreamSynchronize(b->stream));
+    const int rc = upload_psi(b, i, psi, false);
+    if (rc) return rc;
+    b->hs[i].steps = 0;
+    if (b->hs[i].p.max_steps > 0 && !b->hs[i].active) {
+        b->hs[i].active = true;
+        b->units_dirty = true;
+        // a revived simulation rejoins at the batch parity
+        if (b->hs[i].frozen_buf != b->parity) {
+            const size_t es = elem_size(b->precision);
+            HIPCHK(hipMemcpyAsync(b->arena + b->hs[i].off_psi[b->parity], b->arena + b->hs[i].off_psi[b->hs[i].frozen_buf],
+                                  nn * es, hipMemcpyDeviceToDevice, b->stream));
+            HIPCHK(hipMemcpyAsync(b->arena + b->hs[i].off_cs[b->parity], b->arena + b->hs[i].off_cs[b->hs[i].frozen_buf],
+                                  b->hs[i].p.n * sizeof(double), hipMemcpyDeviceToDevice, b->stream));
+            HIPCHK(hipStreamSynchronize(b->stream));
+        }
+    }
+    return VFP_OK;
+}
+
+int vfp_set_psi(vfp_sim *sim, const double *psi) { return vfp_batch_set_psi(sim, 0, psi); }
+
+int vfp_batch_record(vfp_batch *b, int32_t every, int64_t cap)
+{
+    if (!b) return fail(VFP_EINVAL, "NULL handle");
+    return record_impl(b, every, cap);
+}
+
+int vfp_record(vfp_sim *sim, int32_t every, int64_t cap) { return vfp_batch_record(sim, every, cap); }
+
+int vfp_batch_read_record(vfp_batch *b, int32_t i, double *out, int64_t *rows)
+{
+    if (!b || i < 0 || i >= b->count) return fail(VFP_EINVAL, "invalid arguments");
+    return read_record_impl(b, i, out, rows);
+}
+
+int vfp_read_record(vfp_sim *sim, double *out, int64_t *rows) { return vfp_batch_read_record(sim, 0, out, rows); }
+
+int vfp_batch_steps_done(vfp_batch *b, int32_t i, int64_t *steps)
+{
+    if (!b || !steps || i < 0 || i >= b->count) return fail(VFP_EINVAL, "invalid arguments");
+    *steps = b->hs[i].steps;
+    return VFP_OK;
+}
+
+int vfp_steps_done(vfp_sim *sim, int64_t *steps) { return vfp_batch_steps_done(sim, 0, steps); }
+
+void vfp_batch_destroy(vfp_batch *b) { free_batch(b); }
+void vfp_destroy(vfp_sim *sim) { free_batch(sim); }
+
+int vfp_batch_set_tuning(vfp_batch *b, int32_t cells_per_unit, int32_t use_graph)
+{
+    if (!b || cells_per_unit < 0) return fail(VFP_EINVAL, "invalid arguments");
+    const int def = b->precision == VFP_FP64 ? 4096 : 8192;
+    const int cells = cells_per_unit ? cells_per_unit : def;
+    if (cells * elem_size(b->precision) * 2 > 128 * 1024)
+        return fail(VFP_EINVAL, "cells_per_unit too large for the workgroup's LDS");
+    if (cells < 16) return fail(VFP_EINVAL, "cells_per_unit too small");
+    HIPCHK(hipStreamSynchronize(b->stream));
+    b->cells = cells;
+    b->use_graph = use_graph != 0;
+    b->units_dirty = true;
+    b->graph_valid = false;
+    return VFP_OK;
+}
+
+int vfp_batch_autotune(vfp_batch *b, int32_t ticks, int32_t *chosen_cells)
+{
+    if (!b || ticks < 1) return fail(VFP_EINVAL, "invalid arguments");
+    HIPCHK(hipStreamSynchronize(b->stream));
+    // save the state of every simulation (both buffers and column sums)
+    std::vector<std::vector<unsigned char>> save(b->count);
+    const size_t es = elem_size(b->precision);
+    for (int s = 0; s < b->count; ++s) {
+        const HostSim &h = b->hs[s];
+        const size_t nn = (size_t)h.p.n * h.p.n;
+        save[s].resize(2 * nn * es + 2 * h.p.n * 8);
+        HIPCHK(hipMemcpy(save[s].data(), b->arena + h.off_psi[0], nn * es, hipMemcpyDeviceToHost));
+        HIPCHK(hipMemcpy(save[s].data() + nn * es, b->arena + h.off_psi[1], nn * es, hipMemcpyDeviceToHost));
+        HIPCHK(hipMemcpy(save[s].data() + 2 * nn * es, b->arena + h.off_cs[0], h.p.n * 8, hipMemcpyDeviceToHost));
+        HIPCHK(hipMemcpy(save[s].data() + 2 * nn * es + h.p.n * 8, b->arena + h.off_cs[1], h.p.n * 8, hipMemcpyDeviceToHost));
+    }
+    const int64_t tick0 = b->tick;
+    const int parity0 = b->parity;
+    const int every0 = b->every;
+    b->every = 0;   // no records during trials
+    std::vector<int> cand = b->precision == VFP_FP64 ? std::vector<int>{1024, 2048, 4096, 8192}
+                                                     : std::vector<int>{2048, 4096, 8192, 16384};
+    hipEvent_t e0, e1;
+    HIPCHK(hipEventCreate(&e0));
+    HIPCHK(hipEventCreate(&e1));
+    float best = 1e30f;
+    int best_c = b->cells;
+    int rc = VFP_OK;
+    for (int c : cand) {
+        if (c * es * 2 > 128 * 1024) continue;
+        b->cells = c;
+        b->units_dirty = true;
+        rc = rebuild_units(b);
+        if (rc) break;
+        // warm up, then time
+        for (int t = 0; t < 2 && rc == VFP_OK; ++t) { rc = launch_tick(b, b->parity); b->parity ^= 1; }
+        if (rc) break;
+        HIPCHK(hipEventRecord(e0, b->stream));
+        for (int t = 0; t < ticks && rc == VFP_OK; ++t) { rc = launch_tick(b, b->parity); b->parity ^= 1; }
+        HIPCHK(hipEventRecord(e1, b->stream));
+        HIPCHK(hipEventSynchronize(e1));
+        float ms = 0.0f;
+        HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+        if (ms < best) { best = ms; best_c = c; }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    // restore
+    for (int s = 0; s < b->count; ++s) {
+        const HostSim &h = b->hs[s];
+        const size_t nn = (size_t)h.p.n * h.p.n;
+        HIPCHK(hipMemcpy(b->arena + h.off_psi[0], save[s].data(), nn * es, hipMemcpyHostToDevice));
+        HIPCHK(hipMemcpy(b->arena + h.off_psi[1], save[s].data() + nn * es, nn * es, hipMemcpyHostToDevice));
+        HIPCHK(hipMemcpy(b->arena + h.off_cs[0], save[s].data() + 2 * nn * es, h.p.n * 8, hipMemcpyHostToDevice));
+        HIPCHK(hipMemcpy(b->arena + h.off_cs[1], save[s].data() + 2 * nn * es + h.p.n * 8, h.p.n * 8, hipMemcpyHostToDevice));
+    }
+    b->tick = tick0;
+    b->parity = parity0;
+    b->every = every0;
+    if (rc) return rc;
+    b->cells = best_c;
+    b->units_dirty = true;
+    b->graph_valid = false;
+    if (chosen_cells) *chosen_cells = best_c;
+    return VFP_OK;
+}
+
+}  // extern "C"

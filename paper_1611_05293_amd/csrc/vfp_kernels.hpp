@@ -1,0 +1,775 @@
+// vfp_kernels.hpp -- gfx950 device code for the VFP split step
+// (arXiv:1611.05293, Sec. III).  Included once, by vfp.hip.
+//
+// Data layout in HBM (per simulation): psi[2][n][n] (double buffer, p index
+// fastest), colsum[2][n] FP64 column sums of the stored density, the wake
+// table wl[2n-1] indexed by lag + n - 1, and the FP64 diagnostics.
+//
+// The stored density psi^ is not renormalised: the physical state is
+// s * psi^ with s = Q0 / (dq dp sum psi^).  Because rotation, kick and
+// damping are linear in psi for a fixed wake, a step multiplies the rotated
+// values by s and uses the wake of s * rho^; the stored result is then the
+// un-renormalised image of the renormalised state, exactly as if the
+// renormalisation had been applied at the end of the previous step
+// (Sec. III.B step composition; the rescaling itself is not in the paper).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace vfp {
+
+constexpr int kThreads = 256;
+constexpr int kWaves = kThreads / 64;
+constexpr int kMaxStrip = 128;      // columns per work unit
+
+enum WakeMode { WAKE_NONE = 0, WAKE_FUSED = 1, WAKE_EXTERNAL = 2 };
+
+struct SimDev {
+    int32_t n, K, rotation, clamp;
+    int32_t renorm, has_wake, M, pad0;
+    int64_t step0;                   // global tick at which this simulation was at step 0
+    double q_min, p_min, dq, dp;
+    double c, s, th, bt;             // cos, sin of dtheta; dtheta; beta*dtheta
+    double kick;                     // dtheta / dp
+    double S, Q0;
+    // displacement of the rotation source in cells: dx = ax0 + i*axi + j*bx,
+    // dy = cy0 + i*cyi + j*by (exact rewriting of the pull map)
+    double ax0, axi, bx, cy0, cyi, by;
+    double pm;                       // p_min / dp
+    double tw;                       // Manhattan drift per p cell: dtheta*dp/dq
+    double tk;                       // Manhattan RF kick: dtheta*dq/dp
+    void *psi[2];
+    double *colsum[2];
+    const double *wl64;              // 2n-1 lags, FP64
+    const float *wl32;               // 2n-1 lags, FP32
+    const uint32_t *afrag;           // matrix-core wake: per lag block, hi/lo fragments
+    float *vext;                     // matrix-core wake output (n)
+    double *sext;                    // renormalisation factor used with vext
+    double *rho_out, *v_out;         // FP64 diagnostics (n each)
+    double *stat;                    // {Q, <q>, sq, <p>, sp, P, s, bad}
+    double *ring;                    // record rows (7 doubles each) or NULL
+    int64_t ring_cap;
+    int64_t *ring_rows;
+};
+
+struct Unit {
+    int32_t sim, i0, w, pad;
+};
+
+// ---------------------------------------------------------------- helpers
+__device__ __forceinline__ double wave_sum(double v)
+{
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+// deterministic block sum (fixed tree); all threads get the result
+__device__ __forceinline__ double block_sum(double v, double *red)
+{
+    v = wave_sum(v);
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    __syncthreads();
+    if (lane == 0) red[wv] = v;
+    __syncthreads();
+    double t = 0.0;
+    for (int k = 0; k < kWaves; ++k) t += red[k];
+    __syncthreads();
+    return t;
+}
+
+// unit index for this block: consecutive units (the strips of one
+// simulation) go to the same XCD, which the dispatcher picks round-robin
+__device__ __forceinline__ int xcd_unit(int b, int G)
+{
+    const int q = G >> 3, r = G & 7;
+    const int x = b & 7, k = b >> 3;
+    return x * q + (x < r ? x : r) + k;
+}
+
+// ----------------------------------------------- Lagrange weights (Sec. III.A)
+// FP64 mirror of the definition: product over the other stencil nodes.
+template <int K>
+__device__ __forceinline__ void lagrange64(double t, double *l)
+{
+#pragma clang fp contract(off)
+    for (int k = 0; k < K; ++k) {
+        double v = 1.0;
+        for (int kk = 0; kk < K; ++kk) {
+            if (kk == k) continue;
+            const int ok = k - (K - 1) / 2, okk = kk - (K - 1) / 2;
+            v *= (t - okk) / (double)(ok - okk);
+        }
+        l[k] = v;
+    }
+}
+
+// FP32 closed forms of the same polynomials (offsets -1,0,1[,2])
+template <int K>
+__device__ __forceinline__ void lagrange32(float t, float *l)
+{
+    if constexpr (K == 4) {
+        const float tp = t + 1.0f, tm = t - 1.0f, t2 = t - 2.0f;
+        const float a = t * tm;                 // t(t-1)
+        const float b = tp * t2;                // (t+1)(t-2)
+        l[0] = a * t2 * (-1.0f / 6.0f);
+        l[1] = b * tm * 0.5f;
+        l[2] = b * t * (-0.5f);
+        l[3] = a * tp * (1.0f / 6.0f);
+    } else {
+        l[0] = 0.5f * t * (t - 1.0f);
+        l[1] = (1.0f - t) * (1.0f + t);
+        l[2] = 0.5f * t * (t + 1.0f);
+    }
+}
+
+template <typename T>
+__device__ __forceinline__ T ld_node(const T *__restrict__ f, int n, int i, int j)
+{
+    return (i >= 0 && i < n && j >= 0 && j < n) ? f[(size_t)i * n + j] : T(0);
+}
+
+// ------------------------------------------------- standard rotation, FP64
+// Same expression order as the definition (no FMA contraction) so that the
+// FP64 path tracks a plain FP64 evaluation to rounding.
+template <int K, bool CLAMP>
+__device__ double rotate_at64(const double *__restrict__ src, const SimDev &sd, int i, int j)
+{
+#pragma clang fp contract(off)
+    const int n = sd.n;
+    const double q = sd.q_min + i * sd.dq;
+    const double pp = sd.p_min + j * sd.dp;
+    const double q0 = q * sd.c - pp * sd.s;
+    const double p0 = q * sd.s + pp * sd.c;
+    const double rx = (q0 - sd.q_min) / sd.dq;
+    const double ry = (p0 - sd.p_min) / sd.dp;
+    const double mx = floor(rx), my = floor(ry);
+    const int ix = (int)mx, iy = (int)my;
+    double lx[K], ly[K];
+    lagrange64<K>(rx - mx, lx);
+    lagrange64<K>(ry - my, ly);
+    double v = 0.0;
+    for (int a = 0; a < K; ++a)
+        for (int b = 0; b < K; ++b)
+            v += lx[a] * ly[b] * ld_node(src, n, ix + a - (K - 1) / 2, iy + b - (K - 1) / 2);
+    if constexpr (CLAMP) {
+        double lo = ld_node(src, n, ix, iy), hi = lo;
+        for (int a = 0; a < 2; ++a)
+            for (int b = 0; b < 2; ++b) {
+                const double f = ld_node(src, n, ix + a, iy + b);
+                lo = f < lo ? f : lo;
+                hi = f > hi ? f : hi;
+            }
+        v = v < lo ? lo : (v > hi ? hi : v);
+    }
+    return v;
+}
+
+// ------------------------------------------------- standard rotation, FP32
+// Source displacement computed in FP64 from the exact linear form, then the
+// fraction and the K x K weighted sum in FP32.
+template <int K, bool CLAMP>
+__device__ float rotate_at32(const float *__restrict__ src, const SimDev &sd, int i, int j,
+                             double Ai, double Ci)
+{
+    const int n = sd.n;
+    const double dx = fma((double)j, sd.bx, Ai);
+    const double dy = fma((double)j, sd.by, Ci);
+    const double fx = floor(dx), fy = floor(dy);
+    const float tx = (float)(dx - fx), ty = (float)(dy - fy);
+    const int mx = i + (int)fx, my = j + (int)fy;
+    float lx[K], ly[K];
+    lagrange32<K>(tx, lx);
+    lagrange32<K>(ty, ly);
+    constexpr int o0 = (K - 1) / 2;
+    float f[K][K];
+    if (mx - o0 >= 0 && mx + K - 1 - o0 < n && my - o0 >= 0 && my + K - 1 - o0 < n) {
+        const float *base = src + (size_t)(mx - o0) * n + (my - o0);
+#pragma unroll
+        for (int a = 0; a < K; ++a)
+#pragma unroll
+            for (int b = 0; b < K; ++b) f[a][b] = base[(size_t)a * n + b];
+    } else {
+#pragma unroll
+        for (int a = 0; a < K; ++a)
+#pragma unroll
+            for (int b = 0; b < K; ++b) f[a][b] = ld_node(src, n, mx - o0 + a, my - o0 + b);
+    }
+    float v = 0.0f;
+#pragma unroll
+    for (int a = 0; a < K; ++a) {
+        float r = 0.0f;
+#pragma unroll
+        for (int b = 0; b < K; ++b) r = fmaf(ly[b], f[a][b], r);
+        v = fmaf(lx[a], r, v);
+    }
+    if constexpr (CLAMP) {
+        const float lo = fminf(fminf(f[o0][o0], f[o0][o0 + 1]), fminf(f[o0 + 1][o0], f[o0 + 1][o0 + 1]));
+        const float hi = fmaxf(fmaxf(f[o0][o0], f[o0][o0 + 1]), fmaxf(f[o0 + 1][o0], f[o0 + 1][o0 + 1]));
+        v = fminf(fmaxf(v, lo), hi);
+    }
+    return v;
+}
+
+// 1-D interpolation of an LDS column (length n) at integer base m and
+// fraction weights l (stencil offsets -(K-1)/2 ..), zero outside [0, n)
+template <typename T, int K, bool CLAMP>
+__device__ __forceinline__ T interp_lds(const T *col, int n, int m, const T *l)
+{
+    constexpr int o0 = (K - 1) / 2;
+    T v = T(0);
+    T f[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        const int jj = m - o0 + k;
+        f[k] = (jj >= 0 && jj < n) ? col[jj] : T(0);
+    }
+#pragma unroll
+    for (int k = 0; k < K; ++k) v += l[k] * f[k];
+    if constexpr (CLAMP) {
+        const T a = f[o0], b = f[o0 + 1];
+        const T lo = a < b ? a : b, hi = a < b ? b : a;
+        v = v < lo ? lo : (v > hi ? hi : v);
+    }
+    return v;
+}
+
+// Visit every (column c < w, row j < n) of a strip with 256 threads, lanes
+// along j (contiguous in memory).
+template <typename F>
+__device__ __forceinline__ void for_strip(int w, int n, F &&body)
+{
+    const int tid = threadIdx.x;
+    if (n >= kThreads) {
+        for (int c = 0; c < w; ++c)
+            for (int j = tid; j < n; j += kThreads) body(c, j);
+    } else {
+        const int G = kThreads / n;
+        const int g = tid / n, j = tid - g * n;
+        if (g < G)
+            for (int c = g; c < w; c += G) body(c, j);
+    }
+}
+
+// =====================================================================
+// The fused step.  One workgroup owns a strip of whole columns
+// (i0 .. i0+w-1, all j) of one simulation:
+//   prologue  s = Q0/Q^ from the FP64 column sums; wake V for the strip's
+//             columns (FP64 / FP32 Toeplitz row slice) or read V from the
+//             matrix-core wake;
+//   phase R   rotated, renormalised values of the strip -> LDS A
+//             (taps read from the previous density in global memory);
+//   phase K   kick along p -> LDS B;
+//   phase F   damping/diffusion, store psi^_{t+1}, and its FP64 column sums.
+// =====================================================================
+template <typename T, int K, int WAKE, bool CLAMP, int ROT>
+__global__ __launch_bounds__(kThreads) void step_kernel(const SimDev *__restrict__ sims,
+                                                        const Unit *__restrict__ units,
+                                                        int nunits, int parity)
+{
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    __shared__ double red[kThreads];
+    __shared__ double sh_shift[kMaxStrip];
+    __shared__ T sh_kw[kMaxStrip][4];
+    __shared__ int sh_km[kMaxStrip];
+    __shared__ double sh_s;
+
+    const int uidx = xcd_unit(blockIdx.x, nunits);
+    const Unit u = units[uidx];
+    const SimDev &sd = sims[u.sim];
+    const int n = sd.n, w = u.w, i0 = u.i0, tid = threadIdx.x;
+    const T *__restrict__ src = (const T *)sd.psi[parity];
+    T *__restrict__ dst = (T *)sd.psi[parity ^ 1];
+    const double *__restrict__ cs = sd.colsum[parity];
+    double *__restrict__ cs_next = sd.colsum[parity ^ 1];
+    T *A = (T *)smem_raw;
+    T *B = A + (size_t)w * n;
+
+    // ---- prologue: renormalisation factor and the wake slice
+    double s;
+    if constexpr (WAKE == WAKE_EXTERNAL) {
+        s = sd.sext[0];
+    } else {
+        double part = 0.0;
+        for (int k = tid; k < n; k += kThreads) part += cs[k];
+        const double Qh = block_sum(part, red) * sd.dq * sd.dp;
+        s = sd.renorm ? sd.Q0 / Qh : 1.0;
+    }
+    if constexpr (WAKE == WAKE_FUSED) {
+        // V_i = S * s * sum_j w[i-j] * dp * colsum_j for the strip's columns
+        const int parts = w <= kThreads ? kThreads / w : 1;
+        const int c = tid / parts, pt = tid - c * parts;
+        double acc = 0.0;
+        if (c < w) {
+            const int i = i0 + c;
+            if constexpr (sizeof(T) == 8) {
+                for (int j = pt; j < n; j += parts) acc += sd.wl64[i - j + n - 1] * (sd.dp * cs[j]);
+            } else {
+                float a32 = 0.0f;
+                int cnt = 0;
+                for (int j = pt; j < n; j += parts) {
+                    a32 = fmaf(sd.wl32[i - j + n - 1], (float)(sd.dp * cs[j]), a32);
+                    if (++cnt == 32) { acc += a32; a32 = 0.0f; cnt = 0; }
+                }
+                acc += a32;
+            }
+        }
+        __syncthreads();
+        red[tid] = acc;
+        __syncthreads();
+        if (tid < w) {
+            double v = 0.0;
+            for (int k = 0; k < parts; ++k) v += red[tid * parts + k];
+            sh_shift[tid] = sd.S * s * v * sd.kick;      // kick shift in cells
+        }
+    } else if constexpr (WAKE == WAKE_EXTERNAL) {
+        if (tid < w) sh_shift[tid] = (double)sd.vext[i0 + tid] * sd.kick;
+    } else {
+        if (tid < w) sh_shift[tid] = 0.0;
+    }
+    if (tid == 0) sh_s = s;
+    __syncthreads();
+    // per-column kick weights (FP32 path): integer base and fraction
+    if constexpr (sizeof(T) == 4) {
+        if (tid < w) {
+            const double sh = sh_shift[tid];
+            const double fl = floor(sh);
+            float l[K];
+            lagrange32<K>((float)(sh - fl), l);
+            for (int k = 0; k < K; ++k) sh_kw[tid][k] = l[k];
+            sh_km[tid] = (int)fl;
+        }
+    }
+    const T sT = (T)sh_s;
+
+    // ---- phase R: rotation -> A
+    if constexpr (ROT == 0) {
+        for_strip(w, n, [&](int c, int j) {
+            const int i = i0 + c;
+            T v;
+            if constexpr (sizeof(T) == 8) {
+                v = rotate_at64<K, CLAMP>((const double *)src, sd, i, j);
+            } else {
+                const double Ai = fma((double)i, sd.axi, sd.ax0);
+                const double Ci = fma((double)i, sd.cyi, sd.cy0);
+                v = rotate_at32<K, CLAMP>((const float *)src, sd, i, j, Ai, Ci);
+            }
+            A[(size_t)c * n + j] = v * sT;
+        });
+        __syncthreads();
+    } else {
+        // Manhattan: drift along q (pull from q - dtheta*p) from global -> B
+        for_strip(w, n, [&](int c, int j) {
+            const int i = i0 + c;
+            T l[K];
+            int m;
+            if constexpr (sizeof(T) == 8) {
+#pragma clang fp contract(off)
+                const double q = sd.q_min + i * sd.dq;
+                const double pp = sd.p_min + j * sd.dp;
+                const double rx = (q - sd.th * pp - sd.q_min) / sd.dq;
+                const double mf = floor(rx);
+                lagrange64<K>(rx - mf, (double *)l);
+                m = (int)mf;
+            } else {
+                const double rx = (double)i - sd.tw * (sd.pm + (double)j);
+                const double mf = floor(rx);
+                lagrange32<K>((float)(rx - mf), (float *)l);
+                m = (int)mf;
+            }
+            constexpr int o0 = (K - 1) / 2;
+            T f[K];
+            T v = T(0);
+            for (int k = 0; k < K; ++k) f[k] = ld_node(src, n, m - o0 + k, j);
+            for (int k = 0; k < K; ++k) v += l[k] * f[k];
+            if (CLAMP) {
+                const T a = f[o0], b = f[o0 + 1];
+                const T lo = a < b ? a : b, hi = a < b ? b : a;
+                v = v < lo ? lo : (v > hi ? hi : v);
+            }
+            B[(size_t)c * n + j] = v;
+        });
+        __syncthreads();
+        // RF kick along p (pull from p + dtheta*q) B -> A
+        for_strip(w, n, [&](int c, int j) {
+            const int i = i0 + c;
+            T l[K];
+            int m;
+            if constexpr (sizeof(T) == 8) {
+#pragma clang fp contract(off)
+                const double q = sd.q_min + i * sd.dq;
+                const double pp = sd.p_min + j * sd.dp;
+                const double ry = (pp + sd.th * q - sd.p_min) / sd.dp;
+                const double mf = floor(ry);
+                lagrange64<K>(ry - mf, (double *)l);
+                m = (int)mf;
+            } else {
+                const double ry = (double)j + sd.tk * (sd.q_min / sd.dq + (double)i);
+                const double mf = floor(ry);
+                lagrange32<K>((float)(ry - mf), (float *)l);
+                m = (int)mf;
+            }
+            A[(size_t)c * n + j] = interp_lds<T, K, CLAMP>(B + (size_t)c * n, n, m, l) * sT;
+        });
+        __syncthreads();
+    }
+
+    // ---- phase K: kick along p, A -> B
+    for_strip(w, n, [&](int c, int j) {
+        const T *col = A + (size_t)c * n;
+        T v;
+        if constexpr (sizeof(T) == 8) {
+#pragma clang fp contract(off)
+            const double r = (double)j + sh_shift[c];
+            const double mf = floor(r);
+            double l[K];
+            lagrange64<K>(r - mf, l);
+            v = interp_lds<double, K, CLAMP>((const double *)col, n, (int)mf, l);
+        } else {
+            v = interp_lds<float, K, CLAMP>((const float *)col, n, j + sh_km[c], (const float *)sh_kw[c]);
+        }
+        B[(size_t)c * n + j] = v;
+    });
+    __syncthreads();
+
+    // ---- phase F: damping/diffusion B -> global and A (for the column sums)
+    for_strip(w, n, [&](int c, int j) {
+        const T *col = B + (size_t)c * n;
+        const T fm = j > 0 ? col[j - 1] : T(0);
+        const T f0 = col[j];
+        const T f1 = j + 1 < n ? col[j + 1] : T(0);
+        const T f2 = j + 2 < n ? col[j + 2] : T(0);
+        T out;
+        if constexpr (sizeof(T) == 8) {
+#pragma clang fp contract(off)
+            const double dp = sd.dp;
+            const double g0 = (sd.p_min + (j - 1) * dp) * fm;
+            const double g1 = (sd.p_min + (j + 0) * dp) * f0;
+            const double g2 = (sd.p_min + (j + 1) * dp) * f1;
+            const double g3 = (sd.p_min + (j + 2) * dp) * f2;
+            const double d1 = (-2.0 * g0 - 3.0 * g1 + 6.0 * g2 - g3) / (6.0 * dp);
+            const double d2 = (fm - 2.0 * f0 + f1) / (dp * dp);
+            out = f0 + sd.bt * (d1 + d2);
+        } else {
+            // psi + bt*[(-2 g_{j-1} - 3 g_j + 6 g_{j+1} - g_{j+2})/(6dp) + (f_{j-1} - 2 f_j + f_{j+1})/dp^2]
+            // with g = p*psi, p_{j+o}/dp = u + o, u = p_min/dp + j
+            const float u = (float)(sd.pm + (double)j);
+            const float k1 = (float)(sd.bt / 6.0), k2 = (float)(sd.bt / (sd.dp * sd.dp));
+            const float em = fmaf(-2.0f * k1, u - 1.0f, k2);
+            const float e0 = fmaf(-3.0f * k1, u, -2.0f * k2);
+            const float e1 = fmaf(6.0f * k1, u + 1.0f, k2);
+            const float e2 = -k1 * (u + 2.0f);
+            out = f0 + fmaf(em, fm, fmaf(e0, f0, fmaf(e1, f1, e2 * f2)));
+        }
+        dst[(size_t)(i0 + c) * n + j] = out;
+        A[(size_t)c * n + j] = out;
+    });
+    __syncthreads();
+
+    // ---- FP64 column sums of the stored density: one wave per column
+    {
+        const int lane = tid & 63, wv = tid >> 6;
+        for (int c = wv; c < w; c += kWaves) {
+            double acc = 0.0;
+            for (int j = lane; j < n; j += 64) acc += (double)A[(size_t)c * n + j];
+            acc = wave_sum(acc);
+            if (lane == 0) cs_next[i0 + c] = acc;
+        }
+    }
+}
+
+// =====================================================================
+// Column sums of a stored density (initial projection after an upload).
+// grid.x: column blocks of 4 (one wave per column), grid.y: simulation.
+// =====================================================================
+template <typename T>
+__global__ __launch_bounds__(kThreads) void project_kernel(const SimDev *__restrict__ sims,
+                                                           const int *__restrict__ which, int parity)
+{
+    const SimDev &sd = sims[which[blockIdx.y]];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int i = blockIdx.x * kWaves + wv;
+    if (i >= sd.n) return;
+    const T *f = (const T *)sd.psi[parity] + (size_t)i * sd.n;
+    double acc = 0.0;
+    for (int j = lane; j < sd.n; j += 64) acc += (double)f[j];
+    acc = wave_sum(acc);
+    if (lane == 0) sd.colsum[parity][i] = acc;
+}
+
+// =====================================================================
+// FP64 diagnostics of the current state (one workgroup per simulation):
+// s, rho = s*dp*colsum, V = S*T(w)*rho (FP64 Toeplitz), P = sum rho V,
+// moments; optionally appends a record row.  Also flags a non-finite sum.
+// dynamic LDS: 2n doubles.
+// =====================================================================
+template <typename T>
+__global__ __launch_bounds__(kThreads) void stats_kernel(const SimDev *__restrict__ sims,
+                                                         const int *__restrict__ which,
+                                                         const int *__restrict__ bufidx,
+                                                         int64_t rec_base, int every, int record)
+{
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    __shared__ double red[kThreads];
+    const SimDev &sd = sims[which[blockIdx.x]];
+    const int n = sd.n, tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const T *f = (const T *)sd.psi[bufidx[blockIdx.x]];
+    double *c0 = (double *)smem_raw;       // column sums
+    double *rho = c0 + n;
+    double spc = 0.0, sppc = 0.0;          // per-thread partials of sum p psi, p^2 psi
+    for (int i = wv; i < n; i += kWaves) {
+        double a0 = 0.0, a1 = 0.0, a2 = 0.0;
+        for (int j = lane; j < n; j += 64) {
+            const double v = (double)f[(size_t)i * n + j];
+            const double p = sd.p_min + j * sd.dp;
+            a0 += v;
+            a1 += p * v;
+            a2 += p * p * v;
+        }
+        a0 = wave_sum(a0);
+        if (lane == 0) c0[i] = a0;
+        spc += a1;
+        sppc += a2;
+    }
+    __syncthreads();
+    double s0 = 0.0, sq = 0.0, sqq = 0.0;
+    for (int i = tid; i < n; i += kThreads) {
+        const double q = sd.q_min + i * sd.dq;
+        s0 += c0[i];
+        sq += q * c0[i];
+        sqq += q * q * c0[i];
+    }
+    s0 = block_sum(s0, red);
+    sq = block_sum(sq, red);
+    sqq = block_sum(sqq, red);
+    const double sp = block_sum(spc, red);
+    const double spp = block_sum(sppc, red);
+    const double Qh = sd.dq * sd.dp * s0;
+    const double s = sd.renorm ? sd.Q0 / Qh : 1.0;
+    for (int i = tid; i < n; i += kThreads) {
+        rho[i] = s * sd.dp * c0[i];
+        sd.rho_out[i] = rho[i];
+    }
+    __syncthreads();
+    double pw = 0.0;
+    for (int i = tid; i < n; i += kThreads) {
+        double v = 0.0;
+        if (sd.has_wake) {
+            for (int j = 0; j < n; ++j) v += sd.wl64[i - j + n - 1] * rho[j];
+            v *= sd.S;
+        }
+        sd.v_out[i] = v;
+        pw += rho[i] * v;
+    }
+    pw = block_sum(pw, red);
+    if (tid == 0) {
+        const double mq = sq / s0, mp = sp / s0;
+        const double st[8] = {s * Qh, mq, sqrt(fmax(sqq / s0 - mq * mq, 0.0)), mp,
+                              sqrt(fmax(spp / s0 - mp * mp, 0.0)), pw, s,
+                              (isfinite(s0) && isfinite(pw)) ? 0.0 : 1.0};
+        for (int k = 0; k < 8; ++k) sd.stat[k] = st[k];
+        if (record && sd.ring) {
+            const int64_t row = *sd.ring_rows;
+            if (row < sd.ring_cap) {
+                double *r = sd.ring + 7 * row;
+                r[0] = (double)(rec_base + (row + 1) * every - sd.step0);
+                for (int k = 0; k < 5; ++k) r[1 + k] = st[k];
+                r[6] = pw;
+            }
+            *sd.ring_rows = row + 1;
+        }
+    }
+}
+
+// =====================================================================
+// Wake table (Sec. II.B, Eq. "wakepotential"): for every lag
+// m in [-(n-1), n-1], wl[m+n-1] = (1/M) sum_{k<M} Re(Z_k e^{2 pi i k m'/M}),
+// m' = m mod M, Z Hermitian-extended (Im Z_0, Im Z_{M/2} ignored).
+// =====================================================================
+__global__ __launch_bounds__(kThreads) void wake_table_kernel(int n, int M, const double *__restrict__ zr,
+                                                              const double *__restrict__ zi,
+                                                              double *__restrict__ wl64,
+                                                              float *__restrict__ wl32)
+{
+    const int idx = blockIdx.x * kThreads + threadIdx.x;
+    if (idx >= 2 * n - 1) return;
+    const int m = idx - (n - 1);
+    const int mm = ((m % M) + M) % M;
+    double acc = 0.0;
+    for (int k = 0; k < M; ++k) {
+        double a, b;
+        if (k == 0 || 2 * k == M) { a = zr[k]; b = 0.0; }
+        else if (2 * k < M)       { a = zr[k]; b = zi[k]; }
+        else                      { a = zr[M - k]; b = -zi[M - k]; }
+        const long long kl = ((long long)k * mm) % M;
+        double sn, cn;
+        sincospi(2.0 * (double)kl / (double)M, &sn, &cn);
+        acc += a * cn - b * sn;
+    }
+    const double v = acc / (double)M;
+    wl64[idx] = v;
+    wl32[idx] = (float)v;
+}
+
+// =====================================================================
+// Matrix-core wake (mixed precision).  The Toeplitz product V = S T rho is
+// rewritten in 16 x 16 blocks: with V and rho viewed as 16 x nb matrices
+// (column J holds entries 16J .. 16J+15), V[:, I] = sum_d T_d rho[:, I-d]
+// where T_d[a][c] = w[16d + a - c] depends only on the block diagonal d.
+// For a tile of 16 output columns every d is one 16x16x16 product, so the
+// N^2 multiply-adds run on the matrix cores.  Operands are split into a
+// high and a low 16-bit part (x = hi + lo) and three products
+// hi*hi + hi*lo + lo*hi are accumulated in FP32.  For FP16 both operands
+// are pre-scaled by powers of two so that the low parts stay normal.
+// =====================================================================
+typedef short  v4s __attribute__((ext_vector_type(4)));
+typedef _Float16 v4h __attribute__((ext_vector_type(4)));
+typedef float  v4f __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ uint16_t f32_to_bf16_rne(float x)
+{
+    uint32_t u = __float_as_uint(x);
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+__device__ __forceinline__ float bf16_to_f32(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
+
+template <bool FP16>
+__device__ __forceinline__ void split16(float x, uint16_t &hi, uint16_t &lo)
+{
+    if constexpr (FP16) {
+        const _Float16 h = (_Float16)x;
+        const _Float16 l = (_Float16)(x - (float)h);
+        hi = __builtin_bit_cast(uint16_t, h);
+        lo = __builtin_bit_cast(uint16_t, l);
+    } else {
+        hi = f32_to_bf16_rne(x);
+        lo = f32_to_bf16_rne(x - bf16_to_f32(hi));
+    }
+}
+
+// Fragments of T_d for every block diagonal d in [-(nb-1), nb-1]: lane l of
+// the A operand holds T_d[l%16][4(l/16) + q], q = 0..3, i.e. the lags
+// 16d + l%16 - 4(l/16) - q.  Layout: frag[(d+nb-1)*256 + l*4 + {0,1}] = hi,
+// {2,3} = lo (two 16-bit values per word).  Lags beyond n-1 are zero.
+template <bool FP16>
+__global__ void wake_frag_kernel(int n, int nb, const double *__restrict__ wl64, double wscale,
+                                 uint32_t *__restrict__ frag)
+{
+    const int idx = blockIdx.x * kThreads + threadIdx.x;
+    if (idx >= (2 * nb - 1) * 64) return;
+    const int d = idx / 64 - (nb - 1), l = idx & 63;
+    uint16_t hi[4], lo[4];
+    for (int q = 0; q < 4; ++q) {
+        const int lag = 16 * d + (l & 15) - 4 * (l >> 4) - q;
+        const double v = (lag > -n && lag < n) ? wl64[lag + n - 1] * wscale : 0.0;
+        split16<FP16>((float)v, hi[q], lo[q]);
+    }
+    uint32_t *o = frag + (size_t)(d + nb - 1) * 256 + l * 4;
+    o[0] = hi[0] | ((uint32_t)hi[1] << 16);
+    o[1] = hi[2] | ((uint32_t)hi[3] << 16);
+    o[2] = lo[0] | ((uint32_t)lo[1] << 16);
+    o[3] = lo[2] | ((uint32_t)lo[3] << 16);
+}
+
+// One workgroup per simulation.  dynamic LDS: 2 * 16*(nb+30) 16-bit values.
+template <bool FP16>
+__global__ __launch_bounds__(kThreads) void wake_mfma_kernel(const SimDev *__restrict__ sims,
+                                                             const int *__restrict__ which, int parity)
+{
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    __shared__ double red[kThreads];
+    const SimDev &sd = sims[which[blockIdx.x]];
+    const int n = sd.n, tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int nb = (n + 15) / 16;
+    const int L = 16 * (nb + 30);
+    uint16_t *rhi = (uint16_t *)smem_raw;
+    uint16_t *rlo = rhi + L;
+    const double *cs = sd.colsum[parity];
+
+    // s = Q0 / Q^ and the power-of-two scale of rho
+    double part = 0.0, mx = 0.0;
+    for (int k = tid; k < n; k += kThreads) {
+        part += cs[k];
+        mx = fmax(mx, fabs(cs[k]));
+    }
+    const double Qh = block_sum(part, red) * sd.dq * sd.dp;
+    const double s = sd.renorm ? sd.Q0 / Qh : 1.0;
+    // block max (deterministic, order-free)
+    for (int off = 32; off > 0; off >>= 1) mx = fmax(mx, __shfl_xor(mx, off, 64));
+    __syncthreads();
+    if (lane == 0) red[wv] = mx;
+    __syncthreads();
+    double rmax = 0.0;
+    for (int k = 0; k < kWaves; ++k) rmax = fmax(rmax, red[k]);
+    rmax *= s * sd.dp;
+    int e = 0;
+    if (FP16 && rmax > 0.0) { frexp(rmax, &e); e = 14 - e; }
+    const double rscale = ldexp(s * sd.dp, e);
+    for (int k = tid; k < L; k += kThreads) {
+        const int j = k - 16 * 15;
+        uint16_t h = 0, l = 0;
+        if (j >= 0 && j < n) split16<FP16>((float)(cs[j] * rscale), h, l);
+        rhi[k] = h;
+        rlo[k] = l;
+    }
+    __syncthreads();
+
+    // acc = 2^ew * 2^e * sum_j w rho_j with rho = s*dp*colsum; sext[1] = 2^-ew
+    const double outscale = ldexp(sd.S, -e) * sd.sext[1];
+    const int tiles = (nb + 15) / 16;
+    const uint32_t *fr = sd.afrag;
+    for (int tile = wv; tile < tiles; tile += kWaves) {
+        const int I0 = 16 * tile;
+        const int dmin = max(-(nb - 1), I0 - (nb - 1));
+        const int dmax = min(nb - 1, I0 + 15);
+        v4f acc = {0.0f, 0.0f, 0.0f, 0.0f};
+        for (int d = dmin; d <= dmax; ++d) {
+            const uint4 a = *(const uint4 *)(fr + (size_t)(d + nb - 1) * 256 + lane * 4);
+            const int bidx = 16 * (I0 + (lane & 15) - d + 15) + 4 * (lane >> 4);
+            const uint2 bh = *(const uint2 *)(rhi + bidx);
+            const uint2 bl = *(const uint2 *)(rlo + bidx);
+            if constexpr (FP16) {
+                const v4h ah = __builtin_bit_cast(v4h, make_uint2(a.x, a.y));
+                const v4h al = __builtin_bit_cast(v4h, make_uint2(a.z, a.w));
+                const v4h bhh = __builtin_bit_cast(v4h, bh);
+                const v4h bll = __builtin_bit_cast(v4h, bl);
+                acc = __builtin_amdgcn_mfma_f32_16x16x16f16(ah, bhh, acc, 0, 0, 0);
+                acc = __builtin_amdgcn_mfma_f32_16x16x16f16(ah, bll, acc, 0, 0, 0);
+                acc = __builtin_amdgcn_mfma_f32_16x16x16f16(al, bhh, acc, 0, 0, 0);
+            } else {
+                const v4s ah = __builtin_bit_cast(v4s, make_uint2(a.x, a.y));
+                const v4s al = __builtin_bit_cast(v4s, make_uint2(a.z, a.w));
+                const v4s bhh = __builtin_bit_cast(v4s, bh);
+                const v4s bll = __builtin_bit_cast(v4s, bl);
+                acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah, bhh, acc, 0, 0, 0);
+                acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah, bll, acc, 0, 0, 0);
+                acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(al, bhh, acc, 0, 0, 0);
+            }
+        }
+        // lane holds D[4(l/16)+q][l%16] -> V[16(I0 + l%16) + 4(l/16) + q]
+        for (int q = 0; q < 4; ++q) {
+            const int i = 16 * (I0 + (lane & 15)) + 4 * (lane >> 4) + q;
+            if (i < n) sd.vext[i] = (float)((double)acc[q] * outscale);
+        }
+    }
+    if (tid == 0) sd.sext[0] = s;
+}
+
+// psi^ <- (T) psi64 ; used by create and set_psi
+template <typename T>
+__global__ void import_kernel(const double *__restrict__ in, T *__restrict__ out, size_t nn)
+{
+    const size_t z = (size_t)blockIdx.x * kThreads + threadIdx.x;
+    if (z < nn) out[z] = (T)in[z];
+}
+
+// psi64 <- s * psi^ (s from the latest diagnostics)
+template <typename T>
+__global__ void export_kernel(const T *__restrict__ in, const double *__restrict__ stat,
+                              double *__restrict__ out, size_t nn)
+{
+    const size_t z = (size_t)blockIdx.x * kThreads + threadIdx.x;
+    if (z < nn) out[z] = stat[6] * (double)in[z];
+}
+
+}  // namespace vfp

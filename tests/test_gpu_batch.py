@@ -1,0 +1,110 @@
+"""GPU parity of the batched form (uneven grids, per-simulation currents and
+impedances, hipGraph replay, matrix-core wake) against the FP64 oracle run
+simulation by simulation."""
+import numpy as np
+import pytest
+
+from paper_1611_05293_amd import inputs, vfp
+from gpu_common import oracle_run, rel_l1, small_sim
+
+pytestmark = pytest.mark.gpu
+
+
+def mixed_sims():
+    return [
+        small_sim(n=32, steps=80, S=0.4, Pi=0.5, seed=1),
+        small_sim(n=48, steps=120, S=1.2, Pi=1.0, seed=2),
+        small_sim(n=64, steps=160, S=2.0, Pi=2.0, seed=3, lo=-7.0, hi=7.0),
+        small_sim(n=100, steps=250, S=0.9, Pi=0.8, seed=4, lo=-8.0, hi=8.0),   # ragged strips
+        small_sim(n=128, steps=320, S=2.4, Pi=0.3, seed=5, lo=-8.0, hi=8.0),
+    ]
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-12), ("fp32", 1e-5), ("bf16", 1e-5), ("fp16", 1e-5)])
+def test_batch_uneven_matches_oracle(precision, tol):
+    sims = mixed_sims()
+    nt = 40
+    b = vfp.Batch([vfp.sim_kwargs(s, precision=precision) for s in sims])
+    b.step(nt)
+    for i, s in enumerate(sims):
+        ref, _, _, _ = oracle_run(s, nt)
+        err = rel_l1(b.get_psi(i), ref)
+        print(f"{precision} sim {i} n={s.n} rel-L1 {err:.3e}")
+        assert err <= tol
+
+
+def test_graph_replay_equals_direct_launches():
+    sims = mixed_sims()
+    a = vfp.Batch([vfp.sim_kwargs(s, precision="fp32") for s in sims])
+    b = vfp.Batch([vfp.sim_kwargs(s, precision="fp32") for s in sims])
+    a.set_tuning(0, use_graph=True)
+    b.set_tuning(0, use_graph=False)
+    a.step(37)
+    b.step(37)
+    for i in range(len(sims)):
+        assert np.array_equal(a.get_psi(i), b.get_psi(i))
+
+
+def test_batch_of_one_equals_plain_form():
+    s = small_sim(n=64)
+    a = vfp.Batch([vfp.sim_kwargs(s, precision="fp32")])
+    b = vfp.Sim(**vfp.sim_kwargs(s, precision="fp32"))
+    a.step(33)
+    b.step(33)
+    assert np.array_equal(a.get_psi(0), b.get_psi())
+
+
+def test_retirement_after_max_steps():
+    sims = mixed_sims()[:3]
+    caps = [10, 25, 0]
+    b = vfp.Batch([vfp.sim_kwargs(s, precision="fp64", max_steps=c) for s, c in zip(sims, caps)])
+    b.step(30)
+    assert [b.steps_done(i) for i in range(3)] == [10, 25, 30]
+    for i, s in enumerate(sims):
+        ref, _, _, _ = oracle_run(s, [10, 25, 30][i])
+        assert rel_l1(b.get_psi(i), ref) <= 1e-12
+
+
+def test_autotune_preserves_state_and_results():
+    sims = mixed_sims()
+    b = vfp.Batch([vfp.sim_kwargs(s, precision="fp32") for s in sims])
+    b.step(5)
+    cells = b.autotune(ticks=4)
+    assert cells in (2048, 4096, 8192, 16384)
+    assert all(b.steps_done(i) == 5 for i in range(len(sims)))
+    b.step(15)
+    for i, s in enumerate(sims):
+        ref, _, _, _ = oracle_run(s, 20)
+        assert rel_l1(b.get_psi(i), ref) <= 1e-5
+
+
+def test_batch_record_and_chaining():
+    sims = mixed_sims()[:2]
+    b = vfp.Batch([vfp.sim_kwargs(s, precision="fp64") for s in sims])
+    b.record(7, 50)
+    b.step(35)
+    for i, s in enumerate(sims):
+        _, rec, _, _ = oracle_run(s, 35, every=7)
+        r = b.read_record(i)
+        assert r.shape == rec.shape and np.allclose(r[:, 1:], rec[:, 1:], rtol=1e-10, atol=1e-13)
+    # adiabatic chaining: the final density of one run seeds the next
+    psi = b.get_psi(0)
+    c = vfp.Sim(**vfp.sim_kwargs(sims[0], precision="fp64", psi0=psi))
+    c.step(5)
+    b.step(5)
+    assert rel_l1(c.get_psi(), b.get_psi(0)) < 1e-13
+
+
+def test_uneven_scan_full_size_sampled():
+    """The 200-simulation scan at its full sizes (128..1024) in the launch
+    configuration of the benchmark; sampled simulations of every size class
+    against the oracle."""
+    sims = inputs.config(5)
+    b = vfp.Batch([vfp.sim_kwargs(s, precision="fp16") for s in sims])
+    nt = 4
+    b.step(nt)
+    for i in (0, 79, 80, 140, 179, 180, 199):
+        ref, _, _, _ = oracle_run(sims[i], nt)
+        err = rel_l1(b.get_psi(i), ref)
+        print(f"cfg5 sim {i} n={sims[i].n} rel-L1 {err:.3e}")
+        assert err <= 1e-5
