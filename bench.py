@@ -1,0 +1,235 @@
+#!/usr/bin/env python3
+"""Benchmark of the batched VFP step on one MI355X.
+
+Workload (default): the uneven 200-simulation parameter scan -- 80 x 128^2,
+60 x 256^2, 40 x 512^2 and 20 x 1024^2 grids, cubic interpolation, steps per
+period 500..4000 (scaled with the grid), parallel-plate CSR impedance with
+random current and shielding, FP32 density with the FP16 hi/lo matrix-core
+wake and FP64 renormalisation.  One "step" is one tick: every simulation
+advances by one of its own time steps.  Prints one JSON line.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "phase-space cell-updates/s (N²·steps·sims/s), batched vs plain, at stated L1 err"
+HBM_PEAK_GBS = 8000.0
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def workload(name):
+    from paper_1611_05293_amd import inputs
+    if name == "scan200":
+        return inputs.config(5), "fp16", (
+            "uneven scan: 200 sims (80x128^2, 60x256^2, 40x512^2, 20x1024^2), K=4, "
+            "steps/period 500-4000, parallel-plate CSR, S~U[0.1,2.5], Pi~U[0.3,3]")
+    if name == "scan64":
+        return inputs.config(4), "bf16", (
+            "scan: 64 sims at 256^2, K=4, 1000 steps/period, S log-spaced 0.1-2.0, Pi in {0.5,1,2}")
+    raise SystemExit(f"unknown workload {name}")
+
+
+def cpu_baseline(sims, seconds):
+    """The FP64 oracle on this host's cores over a bounded sample of the same
+    workload: the simulations picked in the workload's size ratio, advanced
+    tick by tick (OpenMP over columns inside each simulation)."""
+    import oracle
+    by_n = {}
+    for i, s in enumerate(sims):
+        by_n.setdefault(s.n, []).append(i)
+    ns = sorted(by_n)
+    counts = {n: max(1, len(by_n[n]) // 20) for n in ns}       # 4:3:2:1 for the scan
+    pick = [i for n in ns for i in by_n[n][:counts[n]]]
+    prep = []
+    for i in pick:
+        s = sims[i]
+        p = oracle.OracleParams.from_recipe(s)
+        zr, zi = s.impedance()
+        w = None if zr is None else oracle.wake_kernel(zr, zi, s.padding * s.n)
+        psi = s.psi0()
+        d = (s.q_max - s.q_min) / (s.n - 1) * (s.p_max - s.p_min) / (s.n - 1)
+        prep.append((p, w, psi, d * psi.sum(), s.n))
+    cells_tick = sum(x[4] ** 2 for x in prep)
+    t0 = time.perf_counter()
+    for p, w, psi, Q0, _ in prep:
+        oracle.run(p, w, psi, 1, Q0)
+    one = time.perf_counter() - t0
+    ticks = max(1, int(seconds / max(one, 1e-6)))
+    t0 = time.perf_counter()
+    for p, w, psi, Q0, _ in prep:
+        oracle.run(p, w, psi, ticks, Q0)
+    dt = time.perf_counter() - t0
+    model = ""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return {
+        "value": cells_tick * ticks / dt, "unit": "cell-updates/s", "cores": oracle.threads(),
+        "kind": "oracle",
+        "sample": f"{len(pick)} sims ({'+'.join(f'{counts[n]}x{n}^2' for n in ns)}) x {ticks} steps, FP64, "
+                  f"{dt:.1f} s on {model or 'host CPU'}",
+    }
+
+
+def parity(b, sims, idxs, nsteps):
+    import oracle
+    worst = 0.0
+    for i in idxs:
+        s = sims[i]
+        p = oracle.OracleParams.from_recipe(s)
+        zr, zi = s.impedance()
+        w = None if zr is None else oracle.wake_kernel(zr, zi, s.padding * s.n)
+        psi = s.psi0()
+        d = (s.q_max - s.q_min) / (s.n - 1) * (s.p_max - s.p_min) / (s.n - 1)
+        ref, _ = oracle.run(p, w, psi, nsteps, d * psi.sum())
+        g = b.get_psi(i)
+        worst = max(worst, float(np.abs(g - ref).sum() / np.abs(ref).sum()))
+    return worst
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1000)
+    ap.add_argument("--warmup", type=int, default=50)
+    ap.add_argument("--workload", default="scan200", choices=["scan200", "scan64"])
+    ap.add_argument("--precision", default=None, help="fp32 | bf16 | fp16 | fp64 (default: the workload's)")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-parity", action="store_true")
+    ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--plain-steps", type=int, default=20)
+    ap.add_argument("--autotune", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        sys.exit(2)
+
+    import torch                          # device memory and the stream only
+    from paper_1611_05293_amd import vfp
+
+    sims, prec, desc = workload(args.workload)
+    prec = args.precision or prec
+    cells_tick = sum(s.n * s.n for s in sims)
+    es = 8 if prec == "fp64" else 4
+    log(f"workload {args.workload}: {len(sims)} sims, {cells_tick} cells per tick, precision {prec}")
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        b = vfp.Batch([vfp.sim_kwargs(s, precision=prec) for s in sims], stream=stream, torch_workspace=True)
+    log("created batch")
+    tuned = None
+    if args.autotune:
+        tuned = b.autotune(ticks=10)
+        log(f"autotuned cells per unit: {tuned}")
+    b.step(args.warmup)
+    torch.cuda.synchronize()
+    log(f"warmup {args.warmup} ticks done")
+    err = None
+    if not args.no_parity and args.warmup > 0:
+        by = {}
+        for i, s in enumerate(sims):
+            by.setdefault(s.n, i)
+        err = parity(b, sims, sorted(by.values()), args.warmup)
+        log(f"parity after {args.warmup} ticks, one sim per grid size: max rel-L1 {err:.3e}")
+
+    # timed region: K ticks replayed from the captured graph
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t_wall = time.perf_counter()
+    e0.record(stream)
+    b.step(args.steps)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t_wall
+    ms = e0.elapsed_time(e1)
+    value = cells_tick * args.steps / (ms / 1e3)
+    log(f"timed {args.steps} ticks: {ms:.2f} ms (wall {wall * 1e3:.1f} ms) -> {value:.4e} cell-updates/s")
+
+    # per-kernel durations with HIP events on the same stream (direct launches)
+    kt_ticks = max(20, min(args.steps, 400))
+    b.kernel_timing(True)
+    b.step(kt_ticks)
+    kt = b.kernel_times()
+    b.kernel_timing(False)
+    step_avg_ms = kt["step_ms"] / max(kt["step_launches"], 1)
+    wake_avg_ms = kt["wake_ms"] / max(kt["wake_launches"], 1) if kt["wake_launches"] else 0.0
+    bytes_launch = cells_tick * 2 * es
+    achieved = bytes_launch / (step_avg_ms / 1e3) / 1e9
+    log(f"step kernel avg {step_avg_ms * 1e3:.1f} us, wake kernel avg {wake_avg_ms * 1e3:.1f} us "
+        f"-> {achieved:.0f} GB/s algorithmic")
+
+    plain = None
+    if not args.no_plain:
+        # the plain per-simulation FP32 form: the same simulations one after another
+        ps = args.plain_steps
+        t_ms = 0.0
+        for i, s in enumerate(sims):
+            g = vfp.Sim(stream=stream, **vfp.sim_kwargs(s, precision="fp32"))
+            torch.cuda.synchronize()
+            a0 = torch.cuda.Event(enable_timing=True)
+            a1 = torch.cuda.Event(enable_timing=True)
+            a0.record(stream)
+            g.step(ps)
+            a1.record(stream)
+            torch.cuda.synchronize()
+            t_ms += a0.elapsed_time(a1)
+            g.close()
+        pv = cells_tick * ps / (t_ms / 1e3)
+        plain = {"value": pv, "unit": "cell-updates/s", "form": "plain per-simulation FP32, sims back-to-back",
+                 "steps_per_sim": ps}
+        log(f"plain form: {pv:.4e} cell-updates/s; batched speed-up {value / pv:.1f}x")
+
+    cpu = None
+    if not args.no_cpu:
+        log("timing the oracle on the host")
+        cpu = cpu_baseline(sims, args.cpu_seconds)
+        log(f"oracle: {cpu['value']:.3e} cell-updates/s on {cpu['cores']} threads")
+
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "cell-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if prec == "fp64" else "f32",
+        "data": "synthetic",
+        "config": {"workload": desc, "form": "batched, one fused launch per tick from a hipGraph",
+                   "wake": {"fp16": "FP16 hi/lo MFMA", "bf16": "BF16 hi/lo MFMA",
+                            "fp32": "FP32 VALU", "fp64": "FP64 VALU"}[prec],
+                   "sims": len(sims), "cells_per_tick": cells_tick,
+                   "cells_per_unit": tuned},
+        "parity": None if err is None else {"max_rel_l1_vs_fp64_oracle": err, "after_steps": args.warmup,
+                                            "sims_checked": "one per grid size"},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "step_kernel", "avg_launch_us": step_avg_ms * 1e3,
+                     "bytes_per_launch": bytes_launch, "wake_kernel_avg_us": wake_avg_ms * 1e3},
+        "plain": plain,
+        "batched_speedup": None if plain is None else value / plain["value"],
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -181,6 +181,15 @@ void vfp_batch_destroy(vfp_batch *b);
  * built-in choice); use_graph = 0 launches every tick directly. */
 int vfp_batch_set_tuning(vfp_batch *b, int32_t cells_per_unit, int32_t use_graph);
 
+/* Per-kernel timing with HIP events on the handle's stream: while enabled,
+ * ticks are launched directly (not from a graph) and every launch of the
+ * fused step kernel and of the matrix-core wake kernel is bracketed by a pair
+ * of events.  Enabling (or disabling) clears the accumulated events.
+ * vfp_batch_kernel_times synchronises and returns
+ * out = {step kernel total ms, step launches, wake kernel total ms, wake launches}. */
+int vfp_batch_kernel_timing(vfp_batch *b, int32_t enable);
+int vfp_batch_kernel_times(vfp_batch *b, double out[4]);
+
 /* Autotuner: times `ticks` ticks for each candidate tile size with HIP
  * events on the batch's stream, keeps the fastest, and returns the chosen
  * cells per unit.  The state is saved and restored around the trials. */

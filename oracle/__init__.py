@@ -8,7 +8,7 @@ The arithmetic lives in ``vfp_oracle.c`` (plain loops, FP64,
 ``-O2 -ffp-contract=off``); this module only builds and marshals.
 """
 from .oracle import (  # noqa: F401
-    OracleParams, build, load, lagrange_weights, wake_kernel, profile, charge,
+    OracleParams, build, load, threads, lagrange_weights, wake_kernel, profile, charge,
     wake, rotate, rotate_manhattan, kick, fokker_planck, moments, csr_power,
     step, run, run_many,
 )

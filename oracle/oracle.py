@@ -56,6 +56,14 @@ class OracleParams:
     z_scale: float = 0.0
     rotation: int = 0          # 0 standard, 1 Manhattan
 
+    @classmethod
+    def from_recipe(cls, s) -> "OracleParams":
+        """From any object with the recipe attributes (n, ranges, steps, ...)."""
+        return cls(n=s.n, q_min=s.q_min, q_max=s.q_max, p_min=s.p_min, p_max=s.p_max,
+                   steps_per_period=s.steps_per_period, beta=s.beta, interp=s.interp,
+                   clamp=s.clamp, renormalize=s.renormalize, padding=s.padding,
+                   z_scale=s.z_scale, rotation=s.rotation)
+
     def c(self) -> _P:
         return _P(self.n, self.q_min, self.q_max, self.p_min, self.p_max,
                   self.steps_per_period, self.beta, self.interp, self.clamp,
@@ -73,6 +81,7 @@ def load():
             build(force=True)
         lib = C.CDLL(_LIB)
         P = C.POINTER(_P)
+        lib.vfo_threads.restype = C.c_int
         lib.vfo_lagrange_weights.argtypes = [C.c_int, C.c_double, _dp]
         lib.vfo_profile.argtypes = [P, _dp, _dp]
         lib.vfo_charge.argtypes = [P, _dp]
@@ -104,6 +113,10 @@ def _a(x, n=None):
 
 def _ptr(x):
     return None if x is None else x.ctypes.data_as(_dp)
+
+
+def threads() -> int:
+    return int(load().vfo_threads())
 
 
 def lagrange_weights(K: int, t: float) -> np.ndarray:

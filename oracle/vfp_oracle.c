@@ -31,6 +31,19 @@
 #include <math.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+/* number of OpenMP threads a parallel loop of the oracle uses */
+int vfo_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
 
 typedef struct {
     int    n;                 /* grid points per axis                          */

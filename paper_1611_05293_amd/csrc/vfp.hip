@@ -183,6 +183,10 @@ struct vfp_batch {
     double *d_stage = nullptr;
     size_t stage_elems = 0;
     size_t lds_step = 0, lds_stats = 0, lds_wake = 0;
+    // per-kernel event timing (direct launches while enabled)
+    bool timing = false;
+    std::vector<hipEvent_t> ev_pool;
+    std::vector<std::pair<int, int>> ev_step, ev_wake;   // (start, stop) indices into ev_pool
 };
 
 namespace {
@@ -279,10 +283,27 @@ bool any_wake(const vfp_batch *b)
     return false;
 }
 
+// record an event of the timing pool on the handle's stream
+int timing_event(vfp_batch *b, int *idx)
+{
+    hipEvent_t e;
+    HIPCHK(hipEventCreate(&e));
+    HIPCHK(hipEventRecord(e, b->stream));
+    b->ev_pool.push_back(e);
+    *idx = (int)b->ev_pool.size() - 1;
+    return VFP_OK;
+}
+
 int launch_tick(vfp_batch *b, int parity)
 {
     if (b->units.empty()) return VFP_OK;
     const bool wake = any_wake(b);
+    int t0 = -1, t1 = -1, t2 = -1;
+    const bool mfma = b->precision >= VFP_MIXED_BF16 && wake;
+    if (b->timing) {
+        int rc = timing_event(b, &t0);
+        if (rc) return rc;
+    }
     if (b->precision == VFP_FP64) {
         if (wake) launch_step_k<double, WAKE_FUSED>(b, parity);
         else launch_step_k<double, WAKE_NONE>(b, parity);
@@ -296,9 +317,23 @@ int launch_tick(vfp_batch *b, int parity)
         lds_limit(wk, b->lds_wake, fp16 ? cur16 : cur8);
         hipLaunchKernelGGL(wk, dim3((unsigned)b->active.size()), dim3(kThreads), b->lds_wake, b->stream,
                            b->d_sd, b->d_active, parity);
+        if (b->timing) {
+            int rc = timing_event(b, &t1);
+            if (rc) return rc;
+        }
         launch_step_k<float, WAKE_EXTERNAL>(b, parity);
     }
     HIPCHK(hipGetLastError());
+    if (b->timing) {
+        int rc = timing_event(b, &t2);
+        if (rc) return rc;
+        if (mfma) {
+            b->ev_wake.push_back({t0, t1});
+            b->ev_step.push_back({t1, t2});
+        } else {
+            b->ev_step.push_back({t0, t2});
+        }
+    }
     return VFP_OK;
 }
 
@@ -398,7 +433,7 @@ int advance(vfp_batch *b, int64_t nticks)
     int rc;
     // graph length: even (keeps the parity) and a multiple of the record cadence
     int G = 0;
-    if (b->use_graph) {
+    if (b->use_graph && !b->timing) {
         G = b->every > 0 ? (b->every % 2 ? 2 * b->every : b->every) : 16;
         while (G < 16) G *= 2;
     }
@@ -464,6 +499,7 @@ void free_batch(vfp_batch *b)
     if (b->d_ring) (void)hipFree(b->d_ring);
     if (b->d_ring_rows) (void)hipFree(b->d_ring_rows);
     if (b->d_stage) (void)hipFree(b->d_stage);
+    for (hipEvent_t e : b->ev_pool) (void)hipEventDestroy(e);
     if (b->own_stream) (void)hipStreamDestroy(b->stream);
     delete b;
 }
@@ -975,6 +1011,40 @@ int vfp_batch_set_tuning(vfp_batch *b, int32_t cells_per_unit, int32_t use_graph
     return VFP_OK;
 }
 
+int vfp_batch_kernel_timing(vfp_batch *b, int32_t enable)
+{
+    if (!b) return fail(VFP_EINVAL, "NULL handle");
+    HIPCHK(hipStreamSynchronize(b->stream));
+    for (hipEvent_t e : b->ev_pool) HIPCHK(hipEventDestroy(e));
+    b->ev_pool.clear();
+    b->ev_step.clear();
+    b->ev_wake.clear();
+    b->timing = enable != 0;
+    return VFP_OK;
+}
+
+int vfp_batch_kernel_times(vfp_batch *b, double out[4])
+{
+    if (!b || !out) return fail(VFP_EINVAL, "invalid arguments");
+    HIPCHK(hipStreamSynchronize(b->stream));
+    double st = 0.0, wk = 0.0;
+    for (const auto &pr : b->ev_step) {
+        float ms = 0.0f;
+        HIPCHK(hipEventElapsedTime(&ms, b->ev_pool[pr.first], b->ev_pool[pr.second]));
+        st += ms;
+    }
+    for (const auto &pr : b->ev_wake) {
+        float ms = 0.0f;
+        HIPCHK(hipEventElapsedTime(&ms, b->ev_pool[pr.first], b->ev_pool[pr.second]));
+        wk += ms;
+    }
+    out[0] = st;
+    out[1] = (double)b->ev_step.size();
+    out[2] = wk;
+    out[3] = (double)b->ev_wake.size();
+    return VFP_OK;
+}
+
 int vfp_batch_autotune(vfp_batch *b, int32_t ticks, int32_t *chosen_cells)
 {
     if (!b || ticks < 1) return fail(VFP_EINVAL, "invalid arguments");
@@ -994,7 +1064,9 @@ int vfp_batch_autotune(vfp_batch *b, int32_t ticks, int32_t *chosen_cells)
     const int64_t tick0 = b->tick;
     const int parity0 = b->parity;
     const int every0 = b->every;
+    const bool timing0 = b->timing;
     b->every = 0;   // no records during trials
+    b->timing = false;
     std::vector<int> cand = b->precision == VFP_FP64 ? std::vector<int>{1024, 2048, 4096, 8192}
                                                      : std::vector<int>{2048, 4096, 8192, 16384};
     hipEvent_t e0, e1;
@@ -1034,6 +1106,7 @@ int vfp_batch_autotune(vfp_batch *b, int32_t ticks, int32_t *chosen_cells)
     b->tick = tick0;
     b->parity = parity0;
     b->every = every0;
+    b->timing = timing0;
     if (rc) return rc;
     b->cells = best_c;
     b->units_dirty = true;

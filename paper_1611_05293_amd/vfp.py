@@ -95,6 +95,8 @@ def load():
             "vfp_batch_destroy": (None, [h]),
             "vfp_batch_set_tuning": (C.c_int, [h, C.c_int32, C.c_int32]),
             "vfp_batch_autotune": (C.c_int, [h, C.c_int32, C.POINTER(C.c_int32)]),
+            "vfp_batch_kernel_timing": (C.c_int, [h, C.c_int32]),
+            "vfp_batch_kernel_times": (C.c_int, [h, _dp]),
         }
         for name, (res, args) in sig.items():
             fn = getattr(lib, name)
@@ -242,6 +244,14 @@ class Batch:
         c = C.c_int32()
         _check(load().vfp_batch_autotune(self._h, int(ticks), C.byref(c)))
         return c.value
+
+    def kernel_timing(self, enable: bool = True):
+        _check(load().vfp_batch_kernel_timing(self._h, int(bool(enable))))
+
+    def kernel_times(self) -> dict:
+        out = np.zeros(4)
+        _check(load().vfp_batch_kernel_times(self._h, _ptr(out)))
+        return {"step_ms": out[0], "step_launches": int(out[1]), "wake_ms": out[2], "wake_launches": int(out[3])}
 
     def close(self):
         if getattr(self, "_h", None):

@@ -12,10 +12,7 @@ def rel_l1(a, b):
 
 
 def oracle_params(sim: inputs.Sim) -> OracleParams:
-    return OracleParams(n=sim.n, q_min=sim.q_min, q_max=sim.q_max, p_min=sim.p_min, p_max=sim.p_max,
-                        steps_per_period=sim.steps_per_period, beta=sim.beta, interp=sim.interp,
-                        clamp=sim.clamp, renormalize=sim.renormalize, padding=sim.padding,
-                        z_scale=sim.z_scale, rotation=sim.rotation)
+    return OracleParams.from_recipe(sim)
 
 
 def oracle_run(sim: inputs.Sim, nsteps: int, psi0=None, every: int = 0):
