@@ -19,6 +19,7 @@
 
 #include "vfp.h"
 #include "vfp_kernels.hpp"
+#include "vfp_step32.hpp"
 
 using namespace vfp;
 
@@ -63,6 +64,7 @@ struct HostSim {
     size_t off_psi[2], off_cs[2], off_wl64, off_wl32, off_frag, off_vext, off_sext, off_rho,
         off_v, off_stat;
     int nb = 0;
+    bool fast = false;       // eligible for the LDS-staged FP32 step kernel
 };
 
 int choose_strip(int n, int cells)
@@ -131,7 +133,7 @@ size_t layout(const vfp_params *p, int count, std::vector<HostSim> *hs)
         h.off_wl64 = off; off = align_up(off + (2 * n - 1) * 8);
         h.off_wl32 = off; off = align_up(off + (2 * n - 1) * 4);
         h.off_frag = off;
-        if (q.precision >= VFP_MIXED_BF16) off = align_up(off + (size_t)(2 * nb - 1) * 256 * 4);
+        if (q.precision >= VFP_MIXED_BF16) off = align_up(off + (size_t)(2 * n - 1) * 2 * sizeof(uint16_t));
         h.off_vext = off; off = align_up(off + n * 4);
         h.off_sext = off; off = align_up(off + 2 * 8);
         h.off_rho = off; off = align_up(off + n * 8);
@@ -183,6 +185,10 @@ struct vfp_batch {
     double *d_stage = nullptr;
     size_t stage_elems = 0;
     size_t lds_step = 0, lds_stats = 0, lds_wake = 0;
+    bool fast = false;             // all active simulations use the FP32 staged kernel
+    std::vector<WakeTile> wtiles;
+    WakeTile *d_wtiles = nullptr;
+    size_t wtiles_cap = 0;
     // per-kernel event timing (direct launches while enabled)
     bool timing = false;
     std::vector<hipEvent_t> ev_pool;
@@ -222,7 +228,9 @@ int rebuild_units(vfp_batch *b)
     for (int s : b->active) {
         const int n = b->hs[s].p.n;
         const int w = choose_strip(n, b->cells);
-        for (int i0 = 0; i0 < n; i0 += w) b->units.push_back(Unit{s, i0, std::min(w, n - i0), 0});
+        const int o0 = (b->K - 1) / 2;
+        for (int i0 = 0; i0 < n; i0 += w)
+            b->units.push_back(Unit{s, i0, std::min(w, n - i0), (kH - o0) * (kSY + 1)});
     }
     if (b->units.size() > b->units_cap) {
         if (b->d_units) HIPCHK(hipFree(b->d_units));
@@ -235,12 +243,45 @@ int rebuild_units(vfp_batch *b)
     if (rc) return rc;
     if (!b->active.empty()) rc = upload(b->d_active, b->active.data(), sizeof(int) * b->active.size(), b->stream);
     if (rc) return rc;
-    // LDS of the fused step: two strip buffers
+    // kernel choice and LDS of the fused step
+    b->fast = b->precision != VFP_FP64 && !b->active.empty();
+    for (int s : b->active) b->fast = b->fast && b->hs[s].fast;
     size_t mx = 0;
-    for (const Unit &u : b->units) mx = std::max(mx, (size_t)u.w * b->hs[u.sim].p.n);
-    b->lds_step = 2 * mx * elem_size(b->precision);
-    if (b->lds_step > 64 * 1024 + 64 * 1024)
+    for (const Unit &u : b->units) {
+        const size_t n = b->hs[u.sim].p.n;
+        const size_t bytes = b->fast ? (2 * (size_t)u.w * (n + 2 * kPad) + (size_t)(u.w + 2 * kH) * kSY) * 4
+                                     : 2 * (size_t)u.w * n * elem_size(b->precision);
+        mx = std::max(mx, bytes);
+    }
+    b->lds_step = mx;
+    if (b->lds_step > 150 * 1024)
         return fail(VFP_EINVAL, "strip does not fit the workgroup's LDS; lower cells_per_unit");
+    // matrix-core wake tiles
+    b->wtiles.clear();
+    b->lds_wake = 0;
+    if (b->precision >= VFP_MIXED_BF16) {
+        for (int s : b->active) {
+            const int nb = (b->hs[s].p.n + 15) / 16;
+            for (int t = 0; t < (nb + 15) / 16; ++t) {
+                b->wtiles.push_back(WakeTile{s, t, 0, 0});
+                const int I0 = 16 * t;
+                const int dmin = std::max(-(nb - 1), I0 - (nb - 1)), dmax = std::min(nb - 1, I0 + 15);
+                const size_t NR = 16 * (16 + dmax - dmin), NL = 16 * (dmax - dmin) + 31;
+                const size_t NLp = (NL + 1 + 3) & ~(size_t)3;
+                b->lds_wake = std::max(b->lds_wake, (2 * NR + 4 * NLp) * sizeof(uint16_t));
+            }
+        }
+        if (b->wtiles.size() > b->wtiles_cap) {
+            if (b->d_wtiles) HIPCHK(hipFree(b->d_wtiles));
+            b->d_wtiles = nullptr;
+            HIPCHK(hipMalloc(&b->d_wtiles, sizeof(WakeTile) * b->wtiles.size()));
+            b->wtiles_cap = b->wtiles.size();
+        }
+        if (!b->wtiles.empty()) {
+            rc = upload(b->d_wtiles, b->wtiles.data(), sizeof(WakeTile) * b->wtiles.size(), b->stream);
+            if (rc) return rc;
+        }
+    }
     b->units_dirty = false;
     b->graph_valid = false;
     return VFP_OK;
@@ -257,9 +298,26 @@ void launch_step_t(vfp_batch *b, int parity)
                        b->d_sd, b->d_units, (int)b->units.size(), parity);
 }
 
+template <int K, int WAKE, bool CL>
+void launch_step32_t(vfp_batch *b, int parity)
+{
+    auto k = step32_kernel<K, WAKE, CL>;
+    static int cur = 0;
+    lds_limit(k, b->lds_step, cur);
+    hipLaunchKernelGGL(k, dim3((unsigned)b->units.size()), dim3(kThreads), b->lds_step, b->stream,
+                       b->d_sd, b->d_units, (int)b->units.size(), parity);
+}
+
 template <typename T, int K, int WAKE>
 void launch_step_w(vfp_batch *b, int parity)
 {
+    if constexpr (sizeof(T) == 4) {
+        if (b->fast) {
+            if (b->clamp) launch_step32_t<K, WAKE, true>(b, parity);
+            else launch_step32_t<K, WAKE, false>(b, parity);
+            return;
+        }
+    }
     if (b->clamp) {
         if (b->rotation) launch_step_t<T, K, WAKE, true, 1>(b, parity);
         else launch_step_t<T, K, WAKE, true, 0>(b, parity);
@@ -312,11 +370,11 @@ int launch_tick(vfp_batch *b, int parity)
         else launch_step_k<float, WAKE_NONE>(b, parity);
     } else {
         const bool fp16 = b->precision == VFP_MIXED_FP16;
-        auto wk = fp16 ? wake_mfma_kernel<true> : wake_mfma_kernel<false>;
+        auto wk = fp16 ? wake_mfma2_kernel<true> : wake_mfma2_kernel<false>;
         static int cur16 = 0, cur8 = 0;
         lds_limit(wk, b->lds_wake, fp16 ? cur16 : cur8);
-        hipLaunchKernelGGL(wk, dim3((unsigned)b->active.size()), dim3(kThreads), b->lds_wake, b->stream,
-                           b->d_sd, b->d_active, parity);
+        hipLaunchKernelGGL(wk, dim3((unsigned)b->wtiles.size()), dim3(64), b->lds_wake, b->stream,
+                           b->d_sd, b->d_wtiles, parity);
         if (b->timing) {
             int rc = timing_event(b, &t1);
             if (rc) return rc;
@@ -496,6 +554,7 @@ void free_batch(vfp_batch *b)
     if (b->d_active) (void)hipFree(b->d_active);
     if (b->d_idx) (void)hipFree(b->d_idx);
     if (b->d_buf01) (void)hipFree(b->d_buf01);
+    if (b->d_wtiles) (void)hipFree(b->d_wtiles);
     if (b->d_ring) (void)hipFree(b->d_ring);
     if (b->d_ring_rows) (void)hipFree(b->d_ring_rows);
     if (b->d_stage) (void)hipFree(b->d_stage);
@@ -594,7 +653,7 @@ int create_impl(const vfp_params *p, int32_t count, void *stream, void *ws, size
     b->K = p[0].interp;
     b->clamp = p[0].clamp;
     b->rotation = p[0].rotation;
-    b->cells = b->precision == VFP_FP64 ? 4096 : 8192;
+    b->cells = 4096;
     b->stream = (hipStream_t)stream;
     if (!b->stream) {
         // graphs cannot be captured on the null stream: use a stream of our own
@@ -688,15 +747,25 @@ int create_impl(const vfp_params *p, int32_t count, void *stream, void *ws, size
         d.colsum[1] = (double *)(A + h.off_cs[1]);
         d.wl64 = (const double *)(A + h.off_wl64);
         d.wl32 = (const float *)(A + h.off_wl32);
-        d.afrag = (const uint32_t *)(A + h.off_frag);
+        d.wsplit = (const uint16_t *)(A + h.off_frag);
         d.vext = (float *)(A + h.off_vext);
         d.sext = (double *)(A + h.off_sext);
         d.rho_out = (double *)(A + h.off_rho);
         d.v_out = (double *)(A + h.off_v);
         d.stat = (double *)(A + h.off_stat);
+        // the staged kernel needs n % 4 == 0 and a rotation source within 2 cells of every
+        // node; dx, dy are linear in (i, j), so the corners bound them
+        double lo = 1e300, hi = -1e300;
+        for (int ci = 0; ci < 2; ++ci)
+            for (int cj = 0; cj < 2; ++cj) {
+                const double i = ci ? q.n - 1 : 0, j = cj ? q.n - 1 : 0;
+                const double dx = d.ax0 + i * d.axi + j * d.bx, dy = d.cy0 + i * d.cyi + j * d.by;
+                lo = std::min(lo, std::min(dx, dy));
+                hi = std::max(hi, std::max(dx, dy));
+            }
+        b->hs[s].fast = q.n % 4 == 0 && q.rotation == VFP_ROT_STANDARD && lo > -2.0 + 1e-9 && hi < 2.0 - 1e-9;
     }
     b->lds_stats = 2 * (size_t)maxn * sizeof(double);
-    b->lds_wake = 2 * 16 * (size_t)(((maxn + 15) / 16) + 30) * sizeof(uint16_t);
     HIPCHK(hipMemsetAsync(b->arena, 0, need, b->stream));
     rc = upload_sims(b);
     if (rc) return bail(rc);
@@ -728,14 +797,13 @@ int create_impl(const vfp_params *p, int32_t count, void *stream, void *ws, size
                 e = 14 - e;
             }
             const double wscale = std::ldexp(1.0, e), wback = std::ldexp(1.0, -e);
-            const int nb = h.nb;
-            const unsigned fb = (unsigned)(((2 * nb - 1) * 64 + kThreads - 1) / kThreads);
+            const unsigned fb = (unsigned)((2 * n - 1 + kThreads - 1) / kThreads);
             if (b->precision == VFP_MIXED_FP16)
-                hipLaunchKernelGGL(wake_frag_kernel<true>, dim3(fb), dim3(kThreads), 0, b->stream, n, nb,
-                                   (const double *)(b->arena + h.off_wl64), wscale, (uint32_t *)(b->arena + h.off_frag));
+                hipLaunchKernelGGL(wake_split_kernel<true>, dim3(fb), dim3(kThreads), 0, b->stream, n,
+                                   (const double *)(b->arena + h.off_wl64), wscale, (uint16_t *)(b->arena + h.off_frag));
             else
-                hipLaunchKernelGGL(wake_frag_kernel<false>, dim3(fb), dim3(kThreads), 0, b->stream, n, nb,
-                                   (const double *)(b->arena + h.off_wl64), wscale, (uint32_t *)(b->arena + h.off_frag));
+                hipLaunchKernelGGL(wake_split_kernel<false>, dim3(fb), dim3(kThreads), 0, b->stream, n,
+                                   (const double *)(b->arena + h.off_wl64), wscale, (uint16_t *)(b->arena + h.off_frag));
             const double sx[2] = {1.0, wback};
             if (upload(b->arena + h.off_sext, sx, sizeof(sx), b->stream))
                 return bail(fail(VFP_EDEVICE, "fragment setup failed"));
@@ -998,7 +1066,7 @@ void vfp_destroy(vfp_sim *sim) { free_batch(sim); }
 int vfp_batch_set_tuning(vfp_batch *b, int32_t cells_per_unit, int32_t use_graph)
 {
     if (!b || cells_per_unit < 0) return fail(VFP_EINVAL, "invalid arguments");
-    const int def = b->precision == VFP_FP64 ? 4096 : 8192;
+    const int def = 4096;
     const int cells = cells_per_unit ? cells_per_unit : def;
     if (cells * elem_size(b->precision) * 2 > 128 * 1024)
         return fail(VFP_EINVAL, "cells_per_unit too large for the workgroup's LDS");
@@ -1080,6 +1148,7 @@ int vfp_batch_autotune(vfp_batch *b, int32_t ticks, int32_t *chosen_cells)
         b->cells = c;
         b->units_dirty = true;
         rc = rebuild_units(b);
+        if (rc == VFP_EINVAL) { rc = VFP_OK; continue; }   // does not fit the LDS
         if (rc) break;
         // warm up, then time
         for (int t = 0; t < 2 && rc == VFP_OK; ++t) { rc = launch_tick(b, b->parity); b->parity ^= 1; }

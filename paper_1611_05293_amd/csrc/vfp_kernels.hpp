@@ -42,7 +42,7 @@ struct SimDev {
     double *colsum[2];
     const double *wl64;              // 2n-1 lags, FP64
     const float *wl32;               // 2n-1 lags, FP32
-    const uint32_t *afrag;           // matrix-core wake: per lag block, hi/lo fragments
+    const uint16_t *wsplit;          // matrix-core wake: hi then lo 16-bit parts of the scaled lags
     float *vext;                     // matrix-core wake output (n)
     double *sext;                    // renormalisation factor used with vext
     double *rho_out, *v_out;         // FP64 diagnostics (n each)
@@ -53,7 +53,8 @@ struct SimDev {
 };
 
 struct Unit {
-    int32_t sim, i0, w, pad;
+    int32_t sim, i0, w;
+    int32_t pad;     // staged kernel: LDS index bias (kH - o0) * (kSY + 1)
 };
 
 // ---------------------------------------------------------------- helpers
@@ -620,6 +621,8 @@ __global__ __launch_bounds__(kThreads) void wake_table_kernel(int n, int M, cons
 // high and a low 16-bit part (x = hi + lo) and three products
 // hi*hi + hi*lo + lo*hi are accumulated in FP32.  For FP16 both operands
 // are pre-scaled by powers of two so that the low parts stay normal.
+// Operand layout of the 16x16x16 instructions: lane l holds A[l%16][4(l/16)+q],
+// B[4(l/16)+q][l%16] and D[4(l/16)+q][l%16], q = 0..3.
 // =====================================================================
 typedef short  v4s __attribute__((ext_vector_type(4)));
 typedef _Float16 v4h __attribute__((ext_vector_type(4)));
@@ -647,112 +650,112 @@ __device__ __forceinline__ void split16(float x, uint16_t &hi, uint16_t &lo)
     }
 }
 
-// Fragments of T_d for every block diagonal d in [-(nb-1), nb-1]: lane l of
-// the A operand holds T_d[l%16][4(l/16) + q], q = 0..3, i.e. the lags
-// 16d + l%16 - 4(l/16) - q.  Layout: frag[(d+nb-1)*256 + l*4 + {0,1}] = hi,
-// {2,3} = lo (two 16-bit values per word).  Lags beyond n-1 are zero.
+// ---------------------------------------------------------------------
+// Matrix-core wake, one wave per (simulation, tile of 16 block columns).
+// The high and low 16-bit parts of the (power-of-two scaled) lag table are
+// made once at set-up (wake_split_kernel).  The wave stages rho's hi/lo
+// parts for the block columns it touches and two copies of its lag range,
+// reversed and offset by one element, so that every lane reads its four
+// consecutive Toeplitz entries as two aligned 32-bit words.
+// ---------------------------------------------------------------------
+struct WakeTile {
+    int32_t sim, tile, pad0, pad1;
+};
+
+// split[lag + n - 1] = hi, split[(2n-1) + lag + n - 1] = lo of w[lag] * wscale
 template <bool FP16>
-__global__ void wake_frag_kernel(int n, int nb, const double *__restrict__ wl64, double wscale,
-                                 uint32_t *__restrict__ frag)
+__global__ void wake_split_kernel(int n, const double *__restrict__ wl64, double wscale, uint16_t *__restrict__ split)
 {
     const int idx = blockIdx.x * kThreads + threadIdx.x;
-    if (idx >= (2 * nb - 1) * 64) return;
-    const int d = idx / 64 - (nb - 1), l = idx & 63;
-    uint16_t hi[4], lo[4];
-    for (int q = 0; q < 4; ++q) {
-        const int lag = 16 * d + (l & 15) - 4 * (l >> 4) - q;
-        const double v = (lag > -n && lag < n) ? wl64[lag + n - 1] * wscale : 0.0;
-        split16<FP16>((float)v, hi[q], lo[q]);
-    }
-    uint32_t *o = frag + (size_t)(d + nb - 1) * 256 + l * 4;
-    o[0] = hi[0] | ((uint32_t)hi[1] << 16);
-    o[1] = hi[2] | ((uint32_t)hi[3] << 16);
-    o[2] = lo[0] | ((uint32_t)lo[1] << 16);
-    o[3] = lo[2] | ((uint32_t)lo[3] << 16);
+    if (idx >= 2 * n - 1) return;
+    uint16_t h, l;
+    split16<FP16>((float)(wl64[idx] * wscale), h, l);
+    split[idx] = h;
+    split[2 * n - 1 + idx] = l;
 }
 
-// One workgroup per simulation.  dynamic LDS: 2 * 16*(nb+30) 16-bit values.
 template <bool FP16>
-__global__ __launch_bounds__(kThreads) void wake_mfma_kernel(const SimDev *__restrict__ sims,
-                                                             const int *__restrict__ which, int parity)
+__global__ __launch_bounds__(64) void wake_mfma2_kernel(const SimDev *__restrict__ sims,
+                                                        const WakeTile *__restrict__ tiles, int parity)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    __shared__ double red[kThreads];
-    const SimDev &sd = sims[which[blockIdx.x]];
-    const int n = sd.n, tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-    const int nb = (n + 15) / 16;
-    const int L = 16 * (nb + 30);
+    const WakeTile wt = tiles[blockIdx.x];
+    const SimDev &sd = sims[wt.sim];
+    const int n = sd.n, lane = threadIdx.x, nb = (n + 15) / 16;
+    const int I0 = 16 * wt.tile;
+    const int dmin = max(-(nb - 1), I0 - (nb - 1)), dmax = min(nb - 1, I0 + 15);
+    const int Jlo = I0 - dmax;
+    const int NR = 16 * (16 + dmax - dmin);            // rho entries of block columns Jlo..Jhi
+    const int Lhi = 16 * dmax + 15;                     // highest lag used
+    const int NL = 16 * (dmax - dmin) + 31;             // lags Lhi-NL+1 .. Lhi
+    const int NLp = (NL + 1 + 3) & ~3;
     uint16_t *rhi = (uint16_t *)smem_raw;
-    uint16_t *rlo = rhi + L;
+    uint16_t *rlo = rhi + NR;
+    uint16_t *c0h = rlo + NR, *c0l = c0h + NLp, *c1h = c0l + NLp, *c1l = c1h + NLp;
     const double *cs = sd.colsum[parity];
 
-    // s = Q0 / Q^ and the power-of-two scale of rho
     double part = 0.0, mx = 0.0;
-    for (int k = tid; k < n; k += kThreads) {
+    for (int k = lane; k < n; k += 64) {
         part += cs[k];
         mx = fmax(mx, fabs(cs[k]));
     }
-    const double Qh = block_sum(part, red) * sd.dq * sd.dp;
-    const double s = sd.renorm ? sd.Q0 / Qh : 1.0;
-    // block max (deterministic, order-free)
+    part = wave_sum(part);
     for (int off = 32; off > 0; off >>= 1) mx = fmax(mx, __shfl_xor(mx, off, 64));
-    __syncthreads();
-    if (lane == 0) red[wv] = mx;
-    __syncthreads();
-    double rmax = 0.0;
-    for (int k = 0; k < kWaves; ++k) rmax = fmax(rmax, red[k]);
-    rmax *= s * sd.dp;
+    const double Qh = part * sd.dq * sd.dp;
+    const double s = sd.renorm ? sd.Q0 / Qh : 1.0;
+    const double rmax = mx * s * sd.dp;
     int e = 0;
     if (FP16 && rmax > 0.0) { frexp(rmax, &e); e = 14 - e; }
     const double rscale = ldexp(s * sd.dp, e);
-    for (int k = tid; k < L; k += kThreads) {
-        const int j = k - 16 * 15;
+    for (int k = lane; k < NR; k += 64) {
+        const int g = 16 * Jlo + k;
         uint16_t h = 0, l = 0;
-        if (j >= 0 && j < n) split16<FP16>((float)(cs[j] * rscale), h, l);
+        if (g >= 0 && g < n) split16<FP16>((float)(cs[g] * rscale), h, l);
         rhi[k] = h;
         rlo[k] = l;
     }
+    const uint16_t *wh = sd.wsplit, *wlo = sd.wsplit + (2 * n - 1);
+    for (int y = lane; y < NL + 1; y += 64) {
+        const int L0 = Lhi - y, L1 = Lhi - y - 1;
+        const bool ok0 = L0 > -n && L0 < n && y < NL, ok1 = L1 > -n && L1 < n && y + 1 < NL;
+        c0h[y] = ok0 ? wh[L0 + n - 1] : (uint16_t)0;
+        c0l[y] = ok0 ? wlo[L0 + n - 1] : (uint16_t)0;
+        c1h[y] = ok1 ? wh[L1 + n - 1] : (uint16_t)0;
+        c1l[y] = ok1 ? wlo[L1 + n - 1] : (uint16_t)0;
+    }
     __syncthreads();
 
-    // acc = 2^ew * 2^e * sum_j w rho_j with rho = s*dp*colsum; sext[1] = 2^-ew
-    const double outscale = ldexp(sd.S, -e) * sd.sext[1];
-    const int tiles = (nb + 15) / 16;
-    const uint32_t *fr = sd.afrag;
-    for (int tile = wv; tile < tiles; tile += kWaves) {
-        const int I0 = 16 * tile;
-        const int dmin = max(-(nb - 1), I0 - (nb - 1));
-        const int dmax = min(nb - 1, I0 + 15);
-        v4f acc = {0.0f, 0.0f, 0.0f, 0.0f};
-        for (int d = dmin; d <= dmax; ++d) {
-            const uint4 a = *(const uint4 *)(fr + (size_t)(d + nb - 1) * 256 + lane * 4);
-            const int bidx = 16 * (I0 + (lane & 15) - d + 15) + 4 * (lane >> 4);
-            const uint2 bh = *(const uint2 *)(rhi + bidx);
-            const uint2 bl = *(const uint2 *)(rlo + bidx);
-            if constexpr (FP16) {
-                const v4h ah = __builtin_bit_cast(v4h, make_uint2(a.x, a.y));
-                const v4h al = __builtin_bit_cast(v4h, make_uint2(a.z, a.w));
-                const v4h bhh = __builtin_bit_cast(v4h, bh);
-                const v4h bll = __builtin_bit_cast(v4h, bl);
-                acc = __builtin_amdgcn_mfma_f32_16x16x16f16(ah, bhh, acc, 0, 0, 0);
-                acc = __builtin_amdgcn_mfma_f32_16x16x16f16(ah, bll, acc, 0, 0, 0);
-                acc = __builtin_amdgcn_mfma_f32_16x16x16f16(al, bhh, acc, 0, 0, 0);
-            } else {
-                const v4s ah = __builtin_bit_cast(v4s, make_uint2(a.x, a.y));
-                const v4s al = __builtin_bit_cast(v4s, make_uint2(a.z, a.w));
-                const v4s bhh = __builtin_bit_cast(v4s, bh);
-                const v4s bll = __builtin_bit_cast(v4s, bl);
-                acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah, bhh, acc, 0, 0, 0);
-                acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah, bll, acc, 0, 0, 0);
-                acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(al, bhh, acc, 0, 0, 0);
-            }
-        }
-        // lane holds D[4(l/16)+q][l%16] -> V[16(I0 + l%16) + 4(l/16) + q]
-        for (int q = 0; q < 4; ++q) {
-            const int i = 16 * (I0 + (lane & 15)) + 4 * (lane >> 4) + q;
-            if (i < n) sd.vext[i] = (float)((double)acc[q] * outscale);
+    const int a = lane & 15, kq = 4 * (lane >> 4);
+    // y0 = Lhi - (16d + a - kq) for d = dmax is 15 - a + kq; even y0 read copy 0 at y0,
+    // odd y0 read copy 1 (shifted by one) at y0 - 1
+    const int y00 = 15 - a + kq;
+    const bool odd = y00 & 1;
+    const uint16_t *ah = odd ? c1h + (y00 - 1) : c0h + y00;
+    const uint16_t *al = odd ? c1l + (y00 - 1) : c0l + y00;
+    v4f acc0 = {0.0f, 0.0f, 0.0f, 0.0f}, acc1 = acc0, acc2 = acc0;
+    for (int d = dmax; d >= dmin; --d) {
+        const int yo = 16 * (dmax - d);
+        const uint2 A_h = make_uint2(*(const uint32_t *)(ah + yo), *(const uint32_t *)(ah + yo + 2));
+        const uint2 A_l = make_uint2(*(const uint32_t *)(al + yo), *(const uint32_t *)(al + yo + 2));
+        const int bidx = 16 * (I0 + a - d - Jlo) + kq;
+        const uint2 B_h = *(const uint2 *)(rhi + bidx);
+        const uint2 B_l = *(const uint2 *)(rlo + bidx);
+        if constexpr (FP16) {
+            acc0 = __builtin_amdgcn_mfma_f32_16x16x16f16(__builtin_bit_cast(v4h, A_h), __builtin_bit_cast(v4h, B_h), acc0, 0, 0, 0);
+            acc1 = __builtin_amdgcn_mfma_f32_16x16x16f16(__builtin_bit_cast(v4h, A_h), __builtin_bit_cast(v4h, B_l), acc1, 0, 0, 0);
+            acc2 = __builtin_amdgcn_mfma_f32_16x16x16f16(__builtin_bit_cast(v4h, A_l), __builtin_bit_cast(v4h, B_h), acc2, 0, 0, 0);
+        } else {
+            acc0 = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(__builtin_bit_cast(v4s, A_h), __builtin_bit_cast(v4s, B_h), acc0, 0, 0, 0);
+            acc1 = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(__builtin_bit_cast(v4s, A_h), __builtin_bit_cast(v4s, B_l), acc1, 0, 0, 0);
+            acc2 = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(__builtin_bit_cast(v4s, A_l), __builtin_bit_cast(v4s, B_h), acc2, 0, 0, 0);
         }
     }
-    if (tid == 0) sd.sext[0] = s;
+    const double outscale = ldexp(sd.S, -e) * sd.sext[1];
+    for (int q = 0; q < 4; ++q) {
+        const int i = 16 * (I0 + a) + kq + q;
+        if (i < n) sd.vext[i] = (float)(((double)acc0[q] + ((double)acc1[q] + (double)acc2[q])) * outscale);
+    }
+    if (wt.tile == 0 && lane == 0) sd.sext[0] = s;
 }
 
 // psi^ <- (T) psi64 ; used by create and set_psi
