@@ -178,8 +178,18 @@ void vfp_batch_destroy(vfp_batch *b);
 
 /* Launch tuning: columns per work unit are chosen per grid size.  cells is
  * the number of phase-space cells one workgroup owns (0 restores the
- * built-in choice); use_graph = 0 launches every tick directly. */
-int vfp_batch_set_tuning(vfp_batch *b, int32_t cells_per_unit, int32_t use_graph);
+ * built-in choice); use_graph = 0 launches every tick directly; staged = 0
+ * keeps the generic step kernel even where the LDS-staged FP32 kernel
+ * applies (same arithmetic definition, different evaluation order). */
+int vfp_batch_set_tuning(vfp_batch *b, int32_t cells_per_unit, int32_t use_graph, int32_t staged);
+
+/* The wake V[0..n-1] that the latest step of simulation i used (taken from
+ * the state at the start of that step), as computed by that step's own
+ * arithmetic (FP64/FP32 Toeplitz row slice or the matrix-core product),
+ * returned as FP64.  For comparing each precision form's wake with the FP64
+ * definition.  VFP_ESTATE when the simulation has no impedance; the values
+ * are undefined before the first step.  FP64 mode keeps it in FP32. */
+int vfp_batch_last_wake(vfp_batch *b, int32_t i, double *V);
 
 /* Per-kernel timing with HIP events on the handle's stream: while enabled,
  * ticks are launched directly (not from a graph) and every launch of the

@@ -186,6 +186,7 @@ struct vfp_batch {
     size_t stage_elems = 0;
     size_t lds_step = 0, lds_stats = 0, lds_wake = 0;
     bool fast = false;             // all active simulations use the FP32 staged kernel
+    bool allow_staged = true;      // tuning: the staged kernel may be used
     std::vector<WakeTile> wtiles;
     WakeTile *d_wtiles = nullptr;
     size_t wtiles_cap = 0;
@@ -244,12 +245,13 @@ int rebuild_units(vfp_batch *b)
     if (!b->active.empty()) rc = upload(b->d_active, b->active.data(), sizeof(int) * b->active.size(), b->stream);
     if (rc) return rc;
     // kernel choice and LDS of the fused step
-    b->fast = b->precision != VFP_FP64 && !b->active.empty();
+    b->fast = b->allow_staged && b->precision != VFP_FP64 && !b->active.empty();
     for (int s : b->active) b->fast = b->fast && b->hs[s].fast;
     size_t mx = 0;
     for (const Unit &u : b->units) {
         const size_t n = b->hs[u.sim].p.n;
-        const size_t bytes = b->fast ? (2 * (size_t)u.w * (n + 2 * kPad) + (size_t)(u.w + 2 * kH) * kSY) * 4
+        const size_t bytes = b->fast ? (2 * (size_t)u.w * (n + 2 * kPad) + (size_t)(u.w + 2 * kH) * kSY +
+                                        (b->rotation ? (size_t)u.w * kSY : 0)) * 4
                                      : 2 * (size_t)u.w * n * elem_size(b->precision);
         mx = std::max(mx, bytes);
     }
@@ -298,10 +300,10 @@ void launch_step_t(vfp_batch *b, int parity)
                        b->d_sd, b->d_units, (int)b->units.size(), parity);
 }
 
-template <int K, int WAKE, bool CL>
+template <int K, int WAKE, bool CL, int ROT>
 void launch_step32_t(vfp_batch *b, int parity)
 {
-    auto k = step32_kernel<K, WAKE, CL>;
+    auto k = step32_kernel<K, WAKE, CL, ROT>;
     static int cur = 0;
     lds_limit(k, b->lds_step, cur);
     hipLaunchKernelGGL(k, dim3((unsigned)b->units.size()), dim3(kThreads), b->lds_step, b->stream,
@@ -313,8 +315,13 @@ void launch_step_w(vfp_batch *b, int parity)
 {
     if constexpr (sizeof(T) == 4) {
         if (b->fast) {
-            if (b->clamp) launch_step32_t<K, WAKE, true>(b, parity);
-            else launch_step32_t<K, WAKE, false>(b, parity);
+            if (b->rotation) {
+                if (b->clamp) launch_step32_t<K, WAKE, true, 1>(b, parity);
+                else launch_step32_t<K, WAKE, false, 1>(b, parity);
+            } else {
+                if (b->clamp) launch_step32_t<K, WAKE, true, 0>(b, parity);
+                else launch_step32_t<K, WAKE, false, 0>(b, parity);
+            }
             return;
         }
     }
@@ -607,22 +614,15 @@ int upload_psi(vfp_batch *b, int s, const double *psi, bool gaussian)
     else
         hipLaunchKernelGGL(project_kernel<float>, dim3(cb, 1), dim3(kThreads), 0, b->stream, b->d_sd, b->d_idx, buf);
     HIPCHK(hipGetLastError());
-    // Q0 from the stats kernel with renormalisation off: stat[0] = dq*dp*sum(psi)
-    const int renorm = b->sd[s].renorm;
-    b->sd[s].renorm = 0;
-    rc = upload_sims(b);
-    if (rc) return rc;
-    rc = launch_stats(b, b->d_idx, b->d_idx + 1, 1, 0);
-    if (rc) return rc;
+    // Q0 = dq*dp*sum(psi0) of the FP64 input (stat[0] is scratch here)
+    double *q0dev = (double *)(b->arena + h.off_stat);
+    hipLaunchKernelGGL(charge64_kernel, dim3(1), dim3(kThreads), 0, b->stream, b->d_stage, nn,
+                       b->sd[s].dq * b->sd[s].dp, q0dev);
+    HIPCHK(hipGetLastError());
     double Q0 = 0.0;
-    HIPCHK(hipMemcpyAsync(&Q0, b->arena + h.off_stat, sizeof(double), hipMemcpyDeviceToHost, b->stream));
+    HIPCHK(hipMemcpyAsync(&Q0, q0dev, sizeof(double), hipMemcpyDeviceToHost, b->stream));
     HIPCHK(hipStreamSynchronize(b->stream));
-    if (!(Q0 > 0.0) || !std::isfinite(Q0)) {
-        b->sd[s].renorm = renorm;
-        upload_sims(b);
-        return fail(VFP_EINVAL, "initial density must have a positive, finite charge");
-    }
-    b->sd[s].renorm = renorm;
+    if (!(Q0 > 0.0) || !std::isfinite(Q0)) return fail(VFP_EINVAL, "initial density must have a positive, finite charge");
     b->sd[s].Q0 = Q0;
     b->sd[s].step0 = b->tick;
     rc = upload_sims(b);
@@ -763,7 +763,18 @@ int create_impl(const vfp_params *p, int32_t count, void *stream, void *ws, size
                 lo = std::min(lo, std::min(dx, dy));
                 hi = std::max(hi, std::max(dx, dy));
             }
-        b->hs[s].fast = q.n % 4 == 0 && q.rotation == VFP_ROT_STANDARD && lo > -2.0 + 1e-9 && hi < 2.0 - 1e-9;
+        if (q.rotation == VFP_ROT_MANHATTAN) {
+            // drift shifts -tw*(p_min/dp + j), RF kick shifts tk*(q_min/dq + i)
+            lo = 1e300;
+            hi = -1e300;
+            for (int e = 0; e < 2; ++e) {
+                const double k = e ? q.n - 1 : 0;
+                const double a = -d.tw * (d.pm + k), c = d.tk * (q.q_min / d.dq + k);
+                lo = std::min(lo, std::min(a, c));
+                hi = std::max(hi, std::max(a, c));
+            }
+        }
+        b->hs[s].fast = q.n % 4 == 0 && lo > -2.0 + 1e-9 && hi < 2.0 - 1e-9;
     }
     b->lds_stats = 2 * (size_t)maxn * sizeof(double);
     HIPCHK(hipMemsetAsync(b->arena, 0, need, b->stream));
@@ -1063,7 +1074,7 @@ int vfp_steps_done(vfp_sim *sim, int64_t *steps) { return vfp_batch_steps_done(s
 void vfp_batch_destroy(vfp_batch *b) { free_batch(b); }
 void vfp_destroy(vfp_sim *sim) { free_batch(sim); }
 
-int vfp_batch_set_tuning(vfp_batch *b, int32_t cells_per_unit, int32_t use_graph)
+int vfp_batch_set_tuning(vfp_batch *b, int32_t cells_per_unit, int32_t use_graph, int32_t staged)
 {
     if (!b || cells_per_unit < 0) return fail(VFP_EINVAL, "invalid arguments");
     const int def = 4096;
@@ -1074,8 +1085,20 @@ int vfp_batch_set_tuning(vfp_batch *b, int32_t cells_per_unit, int32_t use_graph
     HIPCHK(hipStreamSynchronize(b->stream));
     b->cells = cells;
     b->use_graph = use_graph != 0;
+    b->allow_staged = staged != 0;
     b->units_dirty = true;
     b->graph_valid = false;
+    return VFP_OK;
+}
+
+int vfp_batch_last_wake(vfp_batch *b, int32_t i, double *V)
+{
+    if (!b || !V || i < 0 || i >= b->count) return fail(VFP_EINVAL, "invalid arguments");
+    if (!b->sd[i].has_wake) return fail(VFP_ESTATE, "simulation has no impedance");
+    HIPCHK(hipStreamSynchronize(b->stream));
+    std::vector<float> v(b->hs[i].p.n);
+    HIPCHK(hipMemcpy(v.data(), b->arena + b->hs[i].off_vext, v.size() * sizeof(float), hipMemcpyDeviceToHost));
+    for (size_t k = 0; k < v.size(); ++k) V[k] = v[k];
     return VFP_OK;
 }
 

@@ -43,7 +43,7 @@ struct SimDev {
     const double *wl64;              // 2n-1 lags, FP64
     const float *wl32;               // 2n-1 lags, FP32
     const uint16_t *wsplit;          // matrix-core wake: hi then lo 16-bit parts of the scaled lags
-    float *vext;                     // matrix-core wake output (n)
+    float *vext;                     // wake used by the latest step (n, FP32)
     double *sext;                    // renormalisation factor used with vext
     double *rho_out, *v_out;         // FP64 diagnostics (n each)
     double *stat;                    // {Q, <q>, sq, <p>, sp, P, s, bad}
@@ -321,6 +321,7 @@ __global__ __launch_bounds__(kThreads) void step_kernel(const SimDev *__restrict
             double v = 0.0;
             for (int k = 0; k < parts; ++k) v += red[tid * parts + k];
             sh_shift[tid] = sd.S * s * v * sd.kick;      // kick shift in cells
+            sd.vext[i0 + tid] = (float)(sd.S * s * v);   // the wake this step used
         }
     } else if constexpr (WAKE == WAKE_EXTERNAL) {
         if (tid < w) sh_shift[tid] = (double)sd.vext[i0 + tid] * sd.kick;
@@ -756,6 +757,18 @@ __global__ __launch_bounds__(64) void wake_mfma2_kernel(const SimDev *__restrict
         if (i < n) sd.vext[i] = (float)(((double)acc0[q] + ((double)acc1[q] + (double)acc2[q])) * outscale);
     }
     if (wt.tile == 0 && lane == 0) sd.sext[0] = s;
+}
+
+// Q0 = dq * dp * sum psi0 of the FP64 input, before any conversion to the
+// storage type (one workgroup, fixed summation order)
+__global__ __launch_bounds__(kThreads) void charge64_kernel(const double *__restrict__ psi, size_t nn, double dqdp,
+                                                            double *__restrict__ out)
+{
+    __shared__ double red[kThreads];
+    double part = 0.0;
+    for (size_t z = threadIdx.x; z < nn; z += kThreads) part += psi[z];
+    const double t = block_sum(part, red);
+    if (threadIdx.x == 0) out[0] = t * dqdp;
 }
 
 // psi^ <- (T) psi64 ; used by create and set_psi

@@ -6,6 +6,7 @@
 //   A[W][n + 2*kPad]   rotated, renormalised values (zero pads of kPad rows)
 //   B[W][n + 2*kPad]   after the kick
 //   S[W + 2*kH][kSY]   the previous density around the current 64-row chunk
+//   Dm[W][kSY]         Manhattan rotation: the drifted chunk
 // Phases:
 //   R  per 64-row chunk: stage S with raw buffer loads (out-of-grid reads
 //      return zero), then every wave interpolates one column of 64 rows
@@ -13,9 +14,11 @@
 //   K  kick along p with per-column weights (whole column in LDS) -> B;
 //   F  damping/diffusion on 4 rows per lane, float4 stores of psi^_{t+1},
 //      FP64 column sums by wave reduction.
-// The source displacement of the rotation must stay below 2 cells in each
-// direction (floor in [-2, 1]); the host routes other grids to the generic
-// kernel.
+// Phase R is either the standard 2-D rotation or the Manhattan pair (drift
+// along q with one shift per row, then RF kick along p with one shift per
+// column, both 1-D).  The source displacement must stay below 2 cells in
+// each direction (floor in [-2, 1]); the host routes other grids to the
+// generic kernel.
 #pragma once
 
 namespace vfp {
@@ -53,7 +56,7 @@ __device__ __forceinline__ void lagrange_fma(float t, float *l)
     }
 }
 
-template <int K, int WAKE, bool CLAMP>
+template <int K, int WAKE, bool CLAMP, int ROT>
 __global__ __launch_bounds__(kThreads) void step32_kernel(const SimDev *__restrict__ sims,
                                                           const Unit *__restrict__ units, int nunits,
                                                           int parity)
@@ -63,6 +66,8 @@ __global__ __launch_bounds__(kThreads) void step32_kernel(const SimDev *__restri
     __shared__ float sh_kw[kMaxStrip][4];
     __shared__ int sh_km[kMaxStrip];
     __shared__ double sh_shift[kMaxStrip];
+    __shared__ float sh_rw[kMaxStrip][4];     // Manhattan RF kick: per-column weights
+    __shared__ int sh_rm[kMaxStrip];          //                   and integer shift
     __shared__ float sh_s;
     constexpr int o0 = (K - 1) / 2;
 
@@ -74,6 +79,7 @@ __global__ __launch_bounds__(kThreads) void step32_kernel(const SimDev *__restri
     float *A = (float *)smem_raw;
     float *B = A + (size_t)W * LA;
     float *S = B + (size_t)W * LA;
+    float *Dm = S + (size_t)(W + 2 * kH) * kSY;     // Manhattan: drifted chunk [W][kSY]
     const float *__restrict__ src = (const float *)sd.psi[parity];
     float *__restrict__ dst = (float *)sd.psi[parity ^ 1];
     const double *__restrict__ cs = sd.colsum[parity];
@@ -110,6 +116,7 @@ __global__ __launch_bounds__(kThreads) void step32_kernel(const SimDev *__restri
             double v = 0.0;
             for (int k = 0; k < parts; ++k) v += red[tid * parts + k];
             sh_shift[tid] = sd.S * s * v * sd.kick;
+            sd.vext[i0 + tid] = (float)(sd.S * s * v);      // the wake this step used
         }
     } else if constexpr (WAKE == WAKE_EXTERNAL) {
         if (tid < W) sh_shift[tid] = (double)sd.vext[i0 + tid] * sd.kick;
@@ -126,6 +133,18 @@ __global__ __launch_bounds__(kThreads) void step32_kernel(const SimDev *__restri
         for (int k = 0; k < K; ++k) sh_kw[tid][k] = l[k];
         for (int k = K; k < 4; ++k) sh_kw[tid][k] = 0.0f;
         sh_km[tid] = (int)fmax(fmin(fl, 1.0e6), -1.0e6);
+    }
+    if constexpr (ROT == 1) {
+        // RF kick of column i pulls along p from p + dtheta*q_i: shift tk*(q_min/dq + i) rows
+        if (tid < W) {
+            const double sh = sd.tk * (sd.q_min / sd.dq + (double)(i0 + tid));
+            const double fl = floor(sh);
+            float l[K];
+            lagrange_fma<K>((float)(sh - fl), l);
+            for (int k = 0; k < K; ++k) sh_rw[tid][k] = l[k];
+            for (int k = K; k < 4; ++k) sh_rw[tid][k] = 0.0f;
+            sh_rm[tid] = (int)fl;
+        }
     }
     for (int k = tid; k < W * 2 * kPad; k += kThreads) {
         const int c = k / (2 * kPad), r = k - c * (2 * kPad);
@@ -145,48 +164,90 @@ __global__ __launch_bounds__(kThreads) void step32_kernel(const SimDev *__restri
             float v0 = 0.0f, v1 = 0.0f;
             if (gi >= 0 && gi < n) {
                 const __amdgpu_buffer_rsrc_t r = column_rsrc(src + (size_t)gi * n, n);
-                v0 = __builtin_amdgcn_raw_buffer_load_b32(r, (j0 - kH + lane) * 4, 0, 0);
-                if (lane < kSY - 64) v1 = __builtin_amdgcn_raw_buffer_load_b32(r, (j0 - kH + 64 + lane) * 4, 0, 0);
+                // the builtin returns the raw 32 bits: reinterpret, do not convert
+                v0 = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, (j0 - kH + lane) * 4, 0, 0));
+                if (lane < kSY - 64)
+                    v1 = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, (j0 - kH + 64 + lane) * 4, 0, 0));
             }
             S[x * kSY + lane] = v0;
             if (lane < kSY - 64) S[x * kSY + 64 + lane] = v1;
         }
         __syncthreads();
-        const int j = j0 + lane;
-        if (j < n) {
-            // source displacement (dx, dy) of column i0+wv, then +kWaves columns per step
-            double dx = fma((double)(i0 + wv), sd.axi, sd.ax0) + (double)j * sd.bx;
-            double dy = fma((double)(i0 + wv), sd.cyi, sd.cy0) + (double)j * sd.by;
-            const double ddx = kWaves * sd.axi, ddy = kWaves * sd.cyi;
-            // LDS index of the first tap: (c + kH + fx - o0) * kSY + lane + kH + fy - o0
-            // u.pad holds (kH - o0) * (kSY + 1) from the host: a run-time value keeps the
-            // tap offsets within the 8-bit dword offsets of ds_read2
-            int cbase = wv * kSY + lane + u.pad;
-            for (int c = wv; c < W; c += kWaves, dx += ddx, dy += ddy, cbase += kWaves * kSY) {
-                const double fx = floor(dx), fy = floor(dy);
-                float lx[K], ly[K];
-                lagrange_fma<K>((float)(dx - fx), lx);
-                lagrange_fma<K>((float)(dy - fy), ly);
-                const float *base = S + (cbase + (int)fma(fx, (double)kSY, fy));
-                float f[K][K];
+        if constexpr (ROT == 0) {
+            const int j = j0 + lane;
+            if (j < n) {
+                // source displacement (dx, dy) of column i0+wv, then +kWaves columns per step
+                double dx = fma((double)(i0 + wv), sd.axi, sd.ax0) + (double)j * sd.bx;
+                double dy = fma((double)(i0 + wv), sd.cyi, sd.cy0) + (double)j * sd.by;
+                const double ddx = kWaves * sd.axi, ddy = kWaves * sd.cyi;
+                // LDS index of the first tap: (c + kH + fx - o0) * kSY + lane + kH + fy - o0
+                // u.pad holds (kH - o0) * (kSY + 1) from the host: a run-time value keeps the
+                // tap offsets within the 8-bit dword offsets of ds_read2
+                int cbase = wv * kSY + lane + u.pad;
+                for (int c = wv; c < W; c += kWaves, dx += ddx, dy += ddy, cbase += kWaves * kSY) {
+                    const double fx = floor(dx), fy = floor(dy);
+                    float lx[K], ly[K];
+                    lagrange_fma<K>((float)(dx - fx), lx);
+                    lagrange_fma<K>((float)(dy - fy), ly);
+                    const float *base = S + (cbase + (int)fma(fx, (double)kSY, fy));
+                    float f[K][K];
 #pragma unroll
-                for (int a = 0; a < K; ++a)
+                    for (int a = 0; a < K; ++a)
 #pragma unroll
-                    for (int b = 0; b < K; ++b) f[a][b] = base[a * kSY + b];
-                float v = 0.0f;
+                        for (int b = 0; b < K; ++b) f[a][b] = base[a * kSY + b];
+                    float v = 0.0f;
 #pragma unroll
-                for (int a = 0; a < K; ++a) {
-                    float r = ly[0] * f[a][0];
+                    for (int a = 0; a < K; ++a) {
+                        float r = ly[0] * f[a][0];
 #pragma unroll
-                    for (int b = 1; b < K; ++b) r = fmaf(ly[b], f[a][b], r);
-                    v = fmaf(lx[a], r, v);
+                        for (int b = 1; b < K; ++b) r = fmaf(ly[b], f[a][b], r);
+                        v = fmaf(lx[a], r, v);
+                    }
+                    if constexpr (CLAMP) {
+                        const float lo = fminf(fminf(f[o0][o0], f[o0][o0 + 1]), fminf(f[o0 + 1][o0], f[o0 + 1][o0 + 1]));
+                        const float hi = fmaxf(fmaxf(f[o0][o0], f[o0][o0 + 1]), fmaxf(f[o0 + 1][o0], f[o0 + 1][o0 + 1]));
+                        v = fminf(fmaxf(v, lo), hi);
+                    }
+                    A[c * LA + kPad + j] = v * sT;
                 }
-                if constexpr (CLAMP) {
-                    const float lo = fminf(fminf(f[o0][o0], f[o0][o0 + 1]), fminf(f[o0 + 1][o0], f[o0 + 1][o0 + 1]));
-                    const float hi = fmaxf(fmaxf(f[o0][o0], f[o0][o0 + 1]), fmaxf(f[o0 + 1][o0], f[o0 + 1][o0 + 1]));
-                    v = fminf(fmaxf(v, lo), hi);
+            }
+        } else {
+            // Manhattan drift: row y of the chunk (global j0 - kH + y) pulls along q from
+            // q - dtheta*p_j, i.e. a shift of -tw*(p_min/dp + j) columns, the same for
+            // every column; rows outside the grid stay zero (their staged rows are zero)
+            for (int y = lane; y < kSY; y += 64) {
+                const double sh = -sd.tw * (sd.pm + (double)(j0 - kH + y));
+                const double fl = floor(sh);
+                float l[K];
+                lagrange_fma<K>((float)(sh - fl), l);
+                const int xo = kH + (int)fl - o0;
+                for (int c = wv; c < W; c += kWaves) {
+                    const float *col = S + (c + xo) * kSY + y;
+                    float f[K];
+#pragma unroll
+                    for (int k = 0; k < K; ++k) f[k] = col[k * kSY];
+                    float v = l[0] * f[0];
+#pragma unroll
+                    for (int k = 1; k < K; ++k) v = fmaf(l[k], f[k], v);
+                    if constexpr (CLAMP) v = fminf(fmaxf(v, fminf(f[o0], f[o0 + 1])), fmaxf(f[o0], f[o0 + 1]));
+                    Dm[c * kSY + y] = v;
                 }
-                A[c * LA + kPad + j] = v * sT;
+            }
+            __syncthreads();
+            // RF kick: column c pulls along p by its own shift sh_rm + fraction
+            const int j = j0 + lane;
+            if (j < n) {
+                for (int c = wv; c < W; c += kWaves) {
+                    const float *col = Dm + c * kSY + lane + kH + sh_rm[c] - o0;
+                    float f[K];
+#pragma unroll
+                    for (int k = 0; k < K; ++k) f[k] = col[k];
+                    float v = sh_rw[c][0] * f[0];
+#pragma unroll
+                    for (int k = 1; k < K; ++k) v = fmaf(sh_rw[c][k], f[k], v);
+                    if constexpr (CLAMP) v = fminf(fmaxf(v, fminf(f[o0], f[o0 + 1])), fmaxf(f[o0], f[o0 + 1]));
+                    A[c * LA + kPad + j] = v * sT;
+                }
             }
         }
     }

@@ -93,9 +93,10 @@ def load():
             "vfp_batch_read_record": (C.c_int, [h, C.c_int32, _dp, C.POINTER(C.c_int64)]),
             "vfp_batch_steps_done": (C.c_int, [h, C.c_int32, C.POINTER(C.c_int64)]),
             "vfp_batch_destroy": (None, [h]),
-            "vfp_batch_set_tuning": (C.c_int, [h, C.c_int32, C.c_int32]),
+            "vfp_batch_set_tuning": (C.c_int, [h, C.c_int32, C.c_int32, C.c_int32]),
             "vfp_batch_autotune": (C.c_int, [h, C.c_int32, C.POINTER(C.c_int32)]),
             "vfp_batch_kernel_timing": (C.c_int, [h, C.c_int32]),
+            "vfp_batch_last_wake": (C.c_int, [h, C.c_int32, _dp]),
             "vfp_batch_kernel_times": (C.c_int, [h, _dp]),
         }
         for name, (res, args) in sig.items():
@@ -237,13 +238,19 @@ class Batch:
         _check(load().vfp_batch_steps_done(self._h, i, C.byref(v)))
         return v.value
 
-    def set_tuning(self, cells_per_unit: int = 0, use_graph: bool = True):
-        _check(load().vfp_batch_set_tuning(self._h, int(cells_per_unit), int(bool(use_graph))))
+    def set_tuning(self, cells_per_unit: int = 0, use_graph: bool = True, staged: bool = True):
+        _check(load().vfp_batch_set_tuning(self._h, int(cells_per_unit), int(bool(use_graph)),
+                                           int(bool(staged))))
 
     def autotune(self, ticks: int = 20) -> int:
         c = C.c_int32()
         _check(load().vfp_batch_autotune(self._h, int(ticks), C.byref(c)))
         return c.value
+
+    def last_wake(self, i: int) -> np.ndarray:
+        out = np.zeros(self.n[i])
+        _check(load().vfp_batch_last_wake(self._h, i, _ptr(out)))
+        return out
 
     def kernel_timing(self, enable: bool = True):
         _check(load().vfp_batch_kernel_timing(self._h, int(bool(enable))))
