@@ -183,6 +183,20 @@ void vfp_batch_destroy(vfp_batch *b);
  * applies (same arithmetic definition, different evaluation order). */
 int vfp_batch_set_tuning(vfp_batch *b, int32_t cells_per_unit, int32_t use_graph, int32_t staged);
 
+/* CSR spectrum of simulation i's current state (Sec. IV.C, P(t,k) ~ Re Z_k
+ * |rho~(k,t)|^2): out[k], k = 0..M/2 (floor(M/2)+1 values, FP64), with
+ * rho~ the DFT of the zero-padded profile and the bins 0 < k < M/2 counting
+ * both k and M-k, so that sum_k out[k] = the CSR power.  Synchronises.
+ * VFP_ESTATE when the simulation has no impedance. */
+int vfp_batch_csr_spectrum(vfp_batch *b, int32_t i, double *out);
+int vfp_csr_spectrum(vfp_sim *sim, double *out);
+
+/* Adiabatic chaining (Appendix A: the final distribution of one run starts
+ * the next): simulation dst takes simulation src's current state on the
+ * device, including its charge Q0; dst's step counter restarts at 0 and a
+ * retired dst rejoins the batch.  Both must have the same grid. */
+int vfp_batch_seed(vfp_batch *b, int32_t dst, int32_t src);
+
 /* The wake V[0..n-1] that the latest step of simulation i used (taken from
  * the state at the start of that step), as computed by that step's own
  * arithmetic (FP64/FP32 Toeplitz row slice or the matrix-core product),

@@ -95,6 +95,7 @@ def load():
         lib.vfo_moments.argtypes = [P, _dp, _dp]
         lib.vfo_csr_power.argtypes = [P, _dp, _dp, _dp, _dp]
         lib.vfo_csr_power.restype = C.c_double
+        lib.vfo_csr_spectrum.argtypes = [P, _dp, _dp, _dp, _dp]
         lib.vfo_step.argtypes = [P, _dp, _dp, C.c_double, _dp]
         lib.vfo_run.argtypes = [P, _dp, _dp, C.c_long, C.c_double, C.c_int, _dp, C.c_long]
         lib.vfo_run.restype = C.c_long
@@ -190,6 +191,14 @@ def csr_power(p: OracleParams, w, psi) -> float:
     rho, V = np.zeros(p.n), np.zeros(p.n)
     return load().vfo_csr_power(C.byref(p.c()), _ptr(_a(w, p.padding * p.n)),
                                 _ptr(_a(psi, p.n * p.n)), _ptr(rho), _ptr(V))
+
+
+def csr_spectrum(p: OracleParams, z_re, psi) -> np.ndarray:
+    M = p.padding * p.n
+    out, rho = np.zeros(M // 2 + 1), np.zeros(p.n)
+    load().vfo_csr_spectrum(C.byref(p.c()), _ptr(_a(z_re, M // 2 + 1)), _ptr(_a(psi, p.n * p.n)),
+                            _ptr(rho), _ptr(out))
+    return out
 
 
 def step(p: OracleParams, w, psi, Q0: float) -> np.ndarray:

@@ -370,6 +370,28 @@ double vfo_csr_power(const vfo_params *p, const double *w, const double *psi, do
     return s;
 }
 
+/* CSR spectrum of the current state (Sec. IV.C): P(k) ~ Re Z_k |rho~_k|^2 */
+/* with rho~_k = sum_j rho_j e^{-2 pi i k j/M} the DFT of the zero-padded */
+/* profile.  Bins k = 0..M/2; the bins 0 < k < M/2 stand for k and M-k, */
+/* so out[k] = (S/M) * m_k * Re Z_k * |rho~_k|^2 with m_k = 2 there and */
+/* 1 at k = 0 and k = M/2 (M even); sum_k out[k] = sum_i rho_i V_i.      */
+void vfo_csr_spectrum(const vfo_params *p, const double *z_re, const double *psi, double *rho, double *out)
+{
+    const int n = p->n, M = p->padding * n;
+    vfo_profile(p, psi, rho);
+    for (int k = 0; k <= M / 2; ++k) {
+        double re = 0.0, im = 0.0;
+        for (int j = 0; j < n; ++j) {
+            const long long kj = ((long long)k * j) % M;
+            const double phi = 2.0 * M_PI * (double)kj / (double)M;
+            re += rho[j] * cos(phi);
+            im -= rho[j] * sin(phi);
+        }
+        const double mult = (k == 0 || 2 * k == M) ? 1.0 : 2.0;
+        out[k] = p->z_scale / (double)M * mult * z_re[k] * (re * re + im * im);
+    }
+}
+
 /* ------------------------------------------------------------------ */
 /* One time step (Sec. III.B, f = f_rot + f_kick + f_damp,diff, applied */
 /* in that order).  The collective force is held constant over the step */

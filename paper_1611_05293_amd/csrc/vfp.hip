@@ -62,7 +62,7 @@ struct HostSim {
     int frozen_buf = 0;      // buffer holding the state once retired
     // arena offsets
     size_t off_psi[2], off_cs[2], off_wl64, off_wl32, off_frag, off_vext, off_sext, off_rho,
-        off_v, off_stat;
+        off_v, off_stat, off_zr;
     int nb = 0;
     bool fast = false;       // eligible for the LDS-staged FP32 step kernel
 };
@@ -139,6 +139,7 @@ size_t layout(const vfp_params *p, int count, std::vector<HostSim> *hs)
         h.off_rho = off; off = align_up(off + n * 8);
         h.off_v = off; off = align_up(off + n * 8);
         h.off_stat = off; off = align_up(off + 8 * 8);
+        h.off_zr = off; off = align_up(off + (size_t)(q.padding * q.n / 2 + 1) * 8);
     }
     return off;
 }
@@ -753,6 +754,7 @@ int create_impl(const vfp_params *p, int32_t count, void *stream, void *ws, size
         d.rho_out = (double *)(A + h.off_rho);
         d.v_out = (double *)(A + h.off_v);
         d.stat = (double *)(A + h.off_stat);
+        d.zr64 = (const double *)(A + h.off_zr);
         // the staged kernel needs n % 4 == 0 and a rotation source within 2 cells of every
         // node; dx, dy are linear in (i, j), so the corners bound them
         double lo = 1e300, hi = -1e300;
@@ -789,6 +791,8 @@ int create_impl(const vfp_params *p, int32_t count, void *stream, void *ws, size
         if (rc) return bail(rc);
         if (upload(b->d_stage, h.zr.data(), nz * sizeof(double), b->stream) ||
             upload(b->d_stage + nz, h.zi.data(), nz * sizeof(double), b->stream))
+            return bail(fail(VFP_EDEVICE, "impedance upload failed"));
+        if (upload(b->arena + h.off_zr, h.zr.data(), nz * sizeof(double), b->stream))
             return bail(fail(VFP_EDEVICE, "impedance upload failed"));
         hipLaunchKernelGGL(wake_table_kernel, dim3((2 * n - 1 + kThreads - 1) / kThreads), dim3(kThreads), 0,
                            b->stream, n, M, b->d_stage, b->d_stage + nz, (double *)(b->arena + h.off_wl64),
@@ -1089,6 +1093,54 @@ int vfp_batch_set_tuning(vfp_batch *b, int32_t cells_per_unit, int32_t use_graph
     b->units_dirty = true;
     b->graph_valid = false;
     return VFP_OK;
+}
+
+int vfp_batch_csr_spectrum(vfp_batch *b, int32_t i, double *out)
+{
+    if (!b || !out || i < 0 || i >= b->count) return fail(VFP_EINVAL, "invalid arguments");
+    if (!b->sd[i].has_wake) return fail(VFP_ESTATE, "simulation has no impedance");
+    int rc = refresh_stats(b);
+    if (rc) return rc;
+    const int nk = b->sd[i].M / 2 + 1;
+    rc = ensure_stage(b, nk);
+    if (rc) return rc;
+    hipLaunchKernelGGL(spectrum_kernel, dim3(1), dim3(kThreads), 0, b->stream, b->d_sd, i, b->d_stage);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipMemcpyAsync(out, b->d_stage, nk * sizeof(double), hipMemcpyDeviceToHost, b->stream));
+    HIPCHK(hipStreamSynchronize(b->stream));
+    return check_finite(b, i);
+}
+
+int vfp_csr_spectrum(vfp_sim *sim, double *out) { return vfp_batch_csr_spectrum(sim, 0, out); }
+
+int vfp_batch_seed(vfp_batch *b, int32_t dst, int32_t src)
+{
+    if (!b || dst < 0 || src < 0 || dst >= b->count || src >= b->count || dst == src)
+        return fail(VFP_EINVAL, "invalid arguments");
+    const vfp_params &a = b->hs[dst].p, &c = b->hs[src].p;
+    if (a.n != c.n || a.q_min != c.q_min || a.q_max != c.q_max || a.p_min != c.p_min || a.p_max != c.p_max)
+        return fail(VFP_EINVAL, "seeding needs the same grid");
+    HIPCHK(hipStreamSynchronize(b->stream));
+    HostSim &hd = b->hs[dst];
+    const HostSim &hsrc = b->hs[src];
+    if (!hd.active) {                         // a retired simulation rejoins at the batch parity
+        hd.active = true;
+        b->units_dirty = true;
+    }
+    const int bs = hsrc.active ? b->parity : hsrc.frozen_buf;
+    const int bd = b->parity;
+    const size_t nn = (size_t)a.n * a.n, es = elem_size(b->precision);
+    HIPCHK(hipMemcpyAsync(b->arena + hd.off_psi[bd], b->arena + hsrc.off_psi[bs], nn * es, hipMemcpyDeviceToDevice,
+                          b->stream));
+    HIPCHK(hipMemcpyAsync(b->arena + hd.off_cs[bd], b->arena + hsrc.off_cs[bs], a.n * sizeof(double),
+                          hipMemcpyDeviceToDevice, b->stream));
+    // the copied density is the source's stored one: its physical state is s*psi^ with the
+    // source's Q0, which the destination takes over
+    b->sd[dst].Q0 = b->sd[src].Q0;
+    b->sd[dst].step0 = b->tick;
+    hd.steps = 0;
+    b->graph_valid = false;
+    return upload_sims(b);
 }
 
 int vfp_batch_last_wake(vfp_batch *b, int32_t i, double *V)

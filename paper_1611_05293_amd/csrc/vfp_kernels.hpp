@@ -46,6 +46,7 @@ struct SimDev {
     float *vext;                     // wake used by the latest step (n, FP32)
     double *sext;                    // renormalisation factor used with vext
     double *rho_out, *v_out;         // FP64 diagnostics (n each)
+    const double *zr64;              // Re Z_k, k = 0..M/2 (CSR spectrum)
     double *stat;                    // {Q, <q>, sq, <p>, sp, P, s, bad}
     double *ring;                    // record rows (7 doubles each) or NULL
     int64_t ring_cap;
@@ -757,6 +758,29 @@ __global__ __launch_bounds__(64) void wake_mfma2_kernel(const SimDev *__restrict
         if (i < n) sd.vext[i] = (float)(((double)acc0[q] + ((double)acc1[q] + (double)acc2[q])) * outscale);
     }
     if (wt.tile == 0 && lane == 0) sd.sext[0] = s;
+}
+
+// CSR spectrum of the state whose profile the diagnostics kernel left in
+// rho_out (Sec. IV.C): out[k] = (S/M) m_k Re Z_k |rho~_k|^2, k = 0..M/2,
+// rho~_k the DFT of the zero-padded profile, m_k = 2 for the bins that stand
+// for k and M-k.  One workgroup per simulation, threads over k.
+__global__ __launch_bounds__(kThreads) void spectrum_kernel(const SimDev *__restrict__ sims, int which,
+                                                            double *__restrict__ out)
+{
+    const SimDev &sd = sims[which];
+    const int n = sd.n, M = sd.M;
+    for (int k = threadIdx.x; k <= M / 2; k += kThreads) {
+        double re = 0.0, im = 0.0;
+        for (int j = 0; j < n; ++j) {
+            const long long kj = ((long long)k * j) % M;
+            double sn, cn;
+            sincospi(2.0 * (double)kj / (double)M, &sn, &cn);
+            re += sd.rho_out[j] * cn;
+            im -= sd.rho_out[j] * sn;
+        }
+        const double mult = (k == 0 || 2 * k == M) ? 1.0 : 2.0;
+        out[k] = sd.S / (double)M * mult * sd.zr64[k] * (re * re + im * im);
+    }
 }
 
 // Q0 = dq * dp * sum psi0 of the FP64 input, before any conversion to the

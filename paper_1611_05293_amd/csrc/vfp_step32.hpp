@@ -27,6 +27,7 @@ constexpr int kPad = 8;            // zero rows above and below each LDS column
 constexpr int kH = 3;              // rotation halo in cells
 constexpr int kJ = 64;             // rows per rotation chunk: one per lane
 constexpr int kSY = kJ + 2 * kH;   // staged rows per chunk
+constexpr int kPF = 10;            // staged columns per wave prefetched into registers
 
 // Raw buffer over one column of n floats: reads outside [0, n) return 0.
 __device__ __forceinline__ __amdgpu_buffer_rsrc_t column_rsrc(const float *col, int n)
@@ -154,17 +155,44 @@ __global__ __launch_bounds__(kThreads) void step32_kernel(const SimDev *__restri
     }
     const float sT = sh_s;       // read after the barrier below
 
-    // ---- phase R: rotation, chunk by chunk
+    // ---- phase R: rotation, chunk by chunk.  The staged rows of chunk k+1 are
+    // loaded into registers (up to kPF columns per wave) while chunk k is
+    // computed; barriers wait on LDS only, so the loads stay in flight.
     const int SX = W + 2 * kH;
+    float pv[kPF][2];
+    auto load_chunk = [&](int j0) {
+#pragma unroll
+        for (int k = 0; k < kPF; ++k) {
+            const int x = wv + kWaves * k;
+            const int gi = i0 - kH + x;
+            pv[k][0] = 0.0f;
+            pv[k][1] = 0.0f;
+            if (x < SX && gi >= 0 && gi < n) {
+                const __amdgpu_buffer_rsrc_t r = column_rsrc(src + (size_t)gi * n, n);
+                // the builtin returns the raw 32 bits: reinterpret, do not convert
+                pv[k][0] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, (j0 - kH + lane) * 4, 0, 0));
+                if (lane < kSY - 64)
+                    pv[k][1] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, (j0 - kH + 64 + lane) * 4, 0, 0));
+            }
+        }
+    };
+    load_chunk(0);
     for (int j0 = 0; j0 < n; j0 += kJ) {
         __syncthreads();
-        // stage S[x][y] = psi(i0 - kH + x, j0 - kH + y), zero outside the grid
-        for (int x = wv; x < SX; x += kWaves) {
+        // S[x][y] = psi(i0 - kH + x, j0 - kH + y), zero outside the grid
+#pragma unroll
+        for (int k = 0; k < kPF; ++k) {
+            const int x = wv + kWaves * k;
+            if (x < SX) {
+                S[x * kSY + lane] = pv[k][0];
+                if (lane < kSY - 64) S[x * kSY + 64 + lane] = pv[k][1];
+            }
+        }
+        for (int x = wv + kWaves * kPF; x < SX; x += kWaves) {      // wide strips: the rest
             const int gi = i0 - kH + x;
             float v0 = 0.0f, v1 = 0.0f;
             if (gi >= 0 && gi < n) {
                 const __amdgpu_buffer_rsrc_t r = column_rsrc(src + (size_t)gi * n, n);
-                // the builtin returns the raw 32 bits: reinterpret, do not convert
                 v0 = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, (j0 - kH + lane) * 4, 0, 0));
                 if (lane < kSY - 64)
                     v1 = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, (j0 - kH + 64 + lane) * 4, 0, 0));
@@ -173,6 +201,7 @@ __global__ __launch_bounds__(kThreads) void step32_kernel(const SimDev *__restri
             if (lane < kSY - 64) S[x * kSY + 64 + lane] = v1;
         }
         __syncthreads();
+        if (j0 + kJ < n) load_chunk(j0 + kJ);
         if constexpr (ROT == 0) {
             const int j = j0 + lane;
             if (j < n) {

@@ -97,6 +97,9 @@ def load():
             "vfp_batch_autotune": (C.c_int, [h, C.c_int32, C.POINTER(C.c_int32)]),
             "vfp_batch_kernel_timing": (C.c_int, [h, C.c_int32]),
             "vfp_batch_last_wake": (C.c_int, [h, C.c_int32, _dp]),
+            "vfp_batch_csr_spectrum": (C.c_int, [h, C.c_int32, _dp]),
+            "vfp_csr_spectrum": (C.c_int, [h, _dp]),
+            "vfp_batch_seed": (C.c_int, [h, C.c_int32, C.c_int32]),
             "vfp_batch_kernel_times": (C.c_int, [h, _dp]),
         }
         for name, (res, args) in sig.items():
@@ -184,6 +187,7 @@ class Batch:
         arr = (Params * len(ps))(*ps)
         self.count = len(ps)
         self.n = [p.n for p in ps]
+        self.M = [p.n * p.padding for p in ps]
         self._ws = None
         ws_ptr, ws_bytes = None, 0
         if torch_workspace:
@@ -247,6 +251,14 @@ class Batch:
         _check(load().vfp_batch_autotune(self._h, int(ticks), C.byref(c)))
         return c.value
 
+    def csr_spectrum(self, i: int) -> np.ndarray:
+        out = np.zeros(self.M[i] // 2 + 1)
+        _check(load().vfp_batch_csr_spectrum(self._h, i, _ptr(out)))
+        return out
+
+    def seed(self, dst: int, src: int):
+        _check(load().vfp_batch_seed(self._h, int(dst), int(src)))
+
     def last_wake(self, i: int) -> np.ndarray:
         out = np.zeros(self.n[i])
         _check(load().vfp_batch_last_wake(self._h, i, _ptr(out)))
@@ -279,6 +291,7 @@ class Sim:
         lib = load()
         p, keep = make_params(**params)
         self.n = p.n
+        self.M = p.n * p.padding
         self._ws = None
         ws_ptr, ws_bytes = None, 0
         if torch_workspace:
@@ -306,6 +319,11 @@ class Sim:
     def moments(self) -> np.ndarray:
         out = np.zeros(5)
         _check(load().vfp_moments(self._h, _ptr(out)))
+        return out
+
+    def csr_spectrum(self) -> np.ndarray:
+        out = np.zeros(self.M // 2 + 1)
+        _check(load().vfp_csr_spectrum(self._h, _ptr(out)))
         return out
 
     def get_psi(self) -> np.ndarray:

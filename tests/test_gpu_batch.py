@@ -108,3 +108,36 @@ def test_uneven_scan_full_size_sampled():
         err = rel_l1(b.get_psi(i), ref)
         print(f"cfg5 sim {i} n={sims[i].n} rel-L1 {err:.3e}")
         assert err <= 1e-5
+
+
+def test_csr_spectrum_matches_oracle():
+    import oracle
+    sim = small_sim(n=64, S=1.5, Pi=0.5)
+    ref, _, w, p = oracle_run(sim, 30)
+    b = vfp.Batch([vfp.sim_kwargs(sim, precision="fp64")])
+    b.step(30)
+    zr, _ = sim.impedance()
+    spec, so = b.csr_spectrum(0), oracle.csr_spectrum(p, zr, ref)
+    assert spec.shape == so.shape == (sim.padding * sim.n // 2 + 1,)
+    assert np.abs(spec - so).max() <= 1e-11 * np.abs(so).max()
+    assert abs(spec.sum() - b.csr_power()[0]) <= 1e-12 * abs(spec.sum())
+
+
+def test_seed_chains_a_current_scan():
+    """Appendix A, adiabatic start: the final state of the run at one current
+    starts the run at the next current, on the device."""
+    import oracle
+    hi_I = small_sim(n=48, S=2.0, Pi=0.7, seed=11)
+    lo_I = small_sim(n=48, S=1.4, Pi=0.7, seed=12)
+    b = vfp.Batch([vfp.sim_kwargs(s, precision="fp64") for s in (hi_I, lo_I)])
+    b.step(20)
+    b.seed(1, 0)
+    assert b.steps_done(1) == 0
+    b.step(15)
+    ref_hi, _, _, _ = oracle_run(hi_I, 20)
+    d = (12 / 47) ** 2
+    Q0 = d * hi_I.psi0().sum()
+    p = oracle.OracleParams.from_recipe(lo_I)
+    zr, zi = lo_I.impedance()
+    ref, _ = oracle.run(p, oracle.wake_kernel(zr, zi, 96), ref_hi, 15, Q0)
+    assert rel_l1(b.get_psi(1), ref) <= 1e-12

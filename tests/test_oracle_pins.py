@@ -375,3 +375,22 @@ def test_haissinski_fixed_point():
     hr /= hr.sum() * dq
     assert np.abs(rn - hr).max() > 10 * np.abs(rn - h).max()
     assert abs(oracle.moments(p, out)[4] - 1.0) < 0.005
+
+
+def test_csr_spectrum_matches_fft_and_sums_to_power():
+    """Sec. IV.C: P(t,k) ~ Re Z_k |rho~(k,t)|^2 and P(t) ~ sum over k.  The
+    oracle's per-bin spectrum equals the numpy FFT route and its bins add up
+    to sum_i rho_i V_i (Parseval)."""
+    n, pad = 40, 2
+    M = pad * n
+    zr, zi = _impedance(M, 17)
+    S = 0.9
+    p = OracleParams(n=n, q_min=-5, q_max=5, p_min=-5, p_max=5, padding=pad, z_scale=S)
+    psi = gauss(n, -5, 5, 1.1, 0.8, q0=0.4)
+    spec = oracle.csr_spectrum(p, zr, psi)
+    rt = np.fft.rfft(oracle.profile(p, psi), M)
+    mult = np.full(M // 2 + 1, 2.0)
+    mult[0] = mult[-1] = 1.0
+    assert np.allclose(spec, S / M * mult * zr * np.abs(rt) ** 2, rtol=1e-12, atol=1e-15)
+    w = oracle.wake_kernel(zr, zi, M)
+    assert abs(spec.sum() - oracle.csr_power(p, w, psi)) < 1e-12 * abs(spec.sum())
