@@ -101,6 +101,30 @@ def parity(b, sims, idxs, nsteps):
     return worst
 
 
+def timed(b, stream, cells_tick, es, steps):
+    """K ticks from the graph between events on the batch's stream, then the
+    per-kernel averages from a pass with events around every launch."""
+    import torch
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    b.step(steps)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    kt_ticks = max(20, min(steps, 400))
+    b.kernel_timing(True)
+    b.step(kt_ticks)
+    kt = b.kernel_times()
+    b.kernel_timing(False)
+    step_ms = kt["step_ms"] / max(kt["step_launches"], 1)
+    wake_ms = kt["wake_ms"] / max(kt["wake_launches"], 1) if kt["wake_launches"] else 0.0
+    nbytes = cells_tick * 2 * es
+    return {"ms": ms, "value": cells_tick * steps / (ms / 1e3), "step_us": step_ms * 1e3, "wake_us": wake_ms * 1e3,
+            "bytes": nbytes, "achieved": nbytes / (step_ms / 1e3) / 1e9}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -114,6 +138,7 @@ def main():
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--plain-steps", type=int, default=20)
     ap.add_argument("--autotune", action="store_true")
+    ap.add_argument("--no-forms", action="store_true", help="skip the FP32 and Manhattan forms")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
@@ -147,31 +172,30 @@ def main():
         log(f"parity after {args.warmup} ticks, one sim per grid size: max rel-L1 {err:.3e}")
 
     # timed region: K ticks replayed from the captured graph
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    t_wall = time.perf_counter()
-    e0.record(stream)
-    b.step(args.steps)
-    e1.record(stream)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t_wall
-    ms = e0.elapsed_time(e1)
-    value = cells_tick * args.steps / (ms / 1e3)
-    log(f"timed {args.steps} ticks: {ms:.2f} ms (wall {wall * 1e3:.1f} ms) -> {value:.4e} cell-updates/s")
+    r = timed(b, stream, cells_tick, es, args.steps)
+    value, ms = r["value"], r["ms"]
+    log(f"timed {args.steps} ticks: {ms:.2f} ms -> {value:.4e} cell-updates/s; step kernel "
+        f"{r['step_us']:.1f} us, wake kernel {r['wake_us']:.1f} us -> {r['achieved']:.0f} GB/s algorithmic")
+    achieved, step_avg_ms, wake_avg_ms, bytes_launch = r["achieved"], r["step_us"] / 1e3, r["wake_us"] / 1e3, r["bytes"]
 
-    # per-kernel durations with HIP events on the same stream (direct launches)
-    kt_ticks = max(20, min(args.steps, 400))
-    b.kernel_timing(True)
-    b.step(kt_ticks)
-    kt = b.kernel_times()
-    b.kernel_timing(False)
-    step_avg_ms = kt["step_ms"] / max(kt["step_launches"], 1)
-    wake_avg_ms = kt["wake_ms"] / max(kt["wake_launches"], 1) if kt["wake_launches"] else 0.0
-    bytes_launch = cells_tick * 2 * es
-    achieved = bytes_launch / (step_avg_ms / 1e3) / 1e9
-    log(f"step kernel avg {step_avg_ms * 1e3:.1f} us, wake kernel avg {wake_avg_ms * 1e3:.1f} us "
-        f"-> {achieved:.0f} GB/s algorithmic")
+    # the same workload in the other forms (same steps; no parity pass)
+    forms = {}
+    if not args.no_forms:
+        for name, fprec, rot in (("fp32_fused_wake", "fp32", 0), ("manhattan_" + prec, prec, 1)):
+            if name.startswith("fp32") and prec == "fp32":
+                continue
+            fb = vfp.Batch([vfp.sim_kwargs(s_, precision=fprec, rotation=rot) for s_ in sims], stream=stream,
+                           torch_workspace=True)
+            fb.step(min(args.warmup, 20))
+            fr = timed(fb, stream, cells_tick, 8 if fprec == "fp64" else 4, args.steps)
+            forms[name] = {"value": fr["value"], "ms_per_step": fr["ms"] / args.steps,
+                           "step_kernel_us": fr["step_us"], "wake_kernel_us": fr["wake_us"],
+                           "hbm_frac": fr["achieved"] / HBM_PEAK_GBS}
+            log(f"form {name}: {fr['value']:.4e} cell-updates/s, step kernel {fr['step_us']:.1f} us "
+                f"({fr['achieved']:.0f} GB/s)")
+            fb.close()
+            del fb
+            torch.cuda.empty_cache()
 
     plain = None
     if not args.no_plain:
@@ -224,6 +248,7 @@ def main():
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None,
                      "kernel": "step_kernel", "avg_launch_us": step_avg_ms * 1e3,
                      "bytes_per_launch": bytes_launch, "wake_kernel_avg_us": wake_avg_ms * 1e3},
+        "forms": forms,
         "plain": plain,
         "batched_speedup": None if plain is None else value / plain["value"],
         "cpu_baseline": cpu,

@@ -191,6 +191,15 @@ int vfp_batch_set_tuning(vfp_batch *b, int32_t cells_per_unit, int32_t use_graph
 int vfp_batch_csr_spectrum(vfp_batch *b, int32_t i, double *out);
 int vfp_csr_spectrum(vfp_sim *sim, double *out);
 
+/* Haissinski start (Appendix A, the equilibrium below threshold): replace
+ * simulation i's state by rho(q) g(p) with rho ~ exp(-q^2/2 - U(q)),
+ * U' = V[rho] its own wake potential, dq*sum(rho) = Q0 (unchanged), and g
+ * the unit Gaussian in p normalised on the grid.  Solved on the device in
+ * FP64 by `iters` damped fixed-point iterations rho <- (1-alpha) rho +
+ * alpha F(rho) from the Gaussian (0 < alpha <= 1).  Step counter restarts. */
+int vfp_batch_haissinski(vfp_batch *b, int32_t i, int32_t iters, double alpha);
+int vfp_haissinski(vfp_sim *sim, int32_t iters, double alpha);
+
 /* Adiabatic chaining (Appendix A: the final distribution of one run starts
  * the next): simulation dst takes simulation src's current state on the
  * device, including its charge Q0; dst's step counter restarts at 0 and a

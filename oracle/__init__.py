@@ -10,5 +10,5 @@ The arithmetic lives in ``vfp_oracle.c`` (plain loops, FP64,
 from .oracle import (  # noqa: F401
     OracleParams, build, load, threads, lagrange_weights, wake_kernel, profile, charge,
     wake, rotate, rotate_manhattan, kick, fokker_planck, moments, csr_power, csr_spectrum,
-    step, run, run_many,
+    step, run, run_many, haissinski,
 )

@@ -96,6 +96,7 @@ def load():
         lib.vfo_csr_power.argtypes = [P, _dp, _dp, _dp, _dp]
         lib.vfo_csr_power.restype = C.c_double
         lib.vfo_csr_spectrum.argtypes = [P, _dp, _dp, _dp, _dp]
+        lib.vfo_haissinski.argtypes = [P, _dp, C.c_int, C.c_double, C.c_double, _dp]
         lib.vfo_step.argtypes = [P, _dp, _dp, C.c_double, _dp]
         lib.vfo_run.argtypes = [P, _dp, _dp, C.c_long, C.c_double, C.c_int, _dp, C.c_long]
         lib.vfo_run.restype = C.c_long
@@ -199,6 +200,13 @@ def csr_spectrum(p: OracleParams, z_re, psi) -> np.ndarray:
     load().vfo_csr_spectrum(C.byref(p.c()), _ptr(_a(z_re, M // 2 + 1)), _ptr(_a(psi, p.n * p.n)),
                             _ptr(rho), _ptr(out))
     return out
+
+
+def haissinski(p: OracleParams, w, iters: int = 200, alpha: float = 0.5, Q0: float = 1.0) -> np.ndarray:
+    out = np.zeros(p.n * p.n)
+    load().vfo_haissinski(C.byref(p.c()), _ptr(_a(w, p.padding * p.n)), int(iters), float(alpha), float(Q0),
+                          _ptr(out))
+    return out.reshape(p.n, p.n)
 
 
 def step(p: OracleParams, w, psi, Q0: float) -> np.ndarray:

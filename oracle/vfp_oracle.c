@@ -393,6 +393,54 @@ void vfo_csr_spectrum(const vfo_params *p, const double *z_re, const double *psi
 }
 
 /* ------------------------------------------------------------------ */
+/* Haissinski starting distribution (Appendix A: the equilibrium profile */
+/* below threshold).  The profile solves rho(q) ~ exp(-q^2/2 - U(q)),     */
+/* U' = V[rho] the wake potential of rho itself, with dq*sum(rho) = Q0;   */
+/* the energy distribution is the unit Gaussian.  Solved by the damped    */
+/* fixed-point iteration rho <- (1-alpha) rho + alpha F(rho), starting    */
+/* from the Gaussian; U by the cumulative trapezoid rule from q_min (its  */
+/* constant drops out in the normalisation).  psi_ij = rho_i g_j with    */
+/* g_j = exp(-p_j^2/2) / (dp sum_j exp(-p_j^2/2)).                        */
+/* ------------------------------------------------------------------ */
+void vfo_haissinski(const vfo_params *p, const double *w, int iters, double alpha, double Q0, double *psi)
+{
+    const int n = p->n;
+    const double dq = grid_dq(p), dp = grid_dp(p);
+    double *rho = (double *)malloc(sizeof(double) * 4 * n);
+    double *V = rho + n, *U = V + n, *F = U + n;
+    double s = 0.0;
+    for (int i = 0; i < n; ++i) {
+        const double q = p->q_min + i * dq;
+        rho[i] = exp(-0.5 * q * q);
+        s += rho[i];
+    }
+    for (int i = 0; i < n; ++i) rho[i] *= Q0 / (dq * s);
+    for (int it = 0; it < iters; ++it) {
+        vfo_wake(p, w, rho, V);
+        U[0] = 0.0;
+        for (int i = 1; i < n; ++i) U[i] = U[i - 1] + 0.5 * (V[i - 1] + V[i]) * dq;
+        s = 0.0;
+        for (int i = 0; i < n; ++i) {
+            const double q = p->q_min + i * dq;
+            F[i] = exp(-0.5 * q * q - U[i]);
+            s += F[i];
+        }
+        for (int i = 0; i < n; ++i) rho[i] = (1.0 - alpha) * rho[i] + alpha * F[i] * (Q0 / (dq * s));
+    }
+    double g = 0.0;
+    for (int j = 0; j < n; ++j) {
+        const double pp = p->p_min + j * dp;
+        g += exp(-0.5 * pp * pp);
+    }
+    for (int i = 0; i < n; ++i)
+        for (int j = 0; j < n; ++j) {
+            const double pp = p->p_min + j * dp;
+            psi[(size_t)i * n + j] = rho[i] * exp(-0.5 * pp * pp) / (dp * g);
+        }
+    free(rho);
+}
+
+/* ------------------------------------------------------------------ */
 /* One time step (Sec. III.B, f = f_rot + f_kick + f_damp,diff, applied */
 /* in that order).  The collective force is held constant over the step */
 /* (Sec. II.A), so rho and V are taken from psi at the start.  After    */

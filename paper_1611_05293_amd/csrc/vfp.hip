@@ -1113,6 +1113,48 @@ int vfp_batch_csr_spectrum(vfp_batch *b, int32_t i, double *out)
 
 int vfp_csr_spectrum(vfp_sim *sim, double *out) { return vfp_batch_csr_spectrum(sim, 0, out); }
 
+int vfp_batch_haissinski(vfp_batch *b, int32_t i, int32_t iters, double alpha)
+{
+    if (!b || i < 0 || i >= b->count || iters < 0 || !(alpha > 0.0 && alpha <= 1.0))
+        return fail(VFP_EINVAL, "invalid arguments");
+    HIPCHK(hipStreamSynchronize(b->stream));
+    HostSim &h = b->hs[i];
+    if (!h.active) {
+        h.active = true;
+        b->units_dirty = true;
+    }
+    const int buf = b->parity, n = h.p.n;
+    const size_t lds = 3 * (size_t)n * sizeof(double);
+    if (b->precision == VFP_FP64) {
+        static int cur = 0;
+        lds_limit(haissinski_kernel<double>, lds, cur);
+        hipLaunchKernelGGL(haissinski_kernel<double>, dim3(1), dim3(kThreads), lds, b->stream, b->d_sd, i, buf, iters,
+                           alpha);
+    } else {
+        static int cur = 0;
+        lds_limit(haissinski_kernel<float>, lds, cur);
+        hipLaunchKernelGGL(haissinski_kernel<float>, dim3(1), dim3(kThreads), lds, b->stream, b->d_sd, i, buf, iters,
+                           alpha);
+    }
+    HIPCHK(hipGetLastError());
+    const int v[2] = {i, buf};
+    int rc = upload(b->d_idx, v, sizeof(v), b->stream);
+    if (rc) return rc;
+    const unsigned cb = (unsigned)((n + kWaves - 1) / kWaves);
+    if (b->precision == VFP_FP64)
+        hipLaunchKernelGGL(project_kernel<double>, dim3(cb, 1), dim3(kThreads), 0, b->stream, b->d_sd, b->d_idx, buf);
+    else
+        hipLaunchKernelGGL(project_kernel<float>, dim3(cb, 1), dim3(kThreads), 0, b->stream, b->d_sd, b->d_idx, buf);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(b->stream));
+    b->sd[i].step0 = b->tick;
+    h.steps = 0;
+    b->graph_valid = false;
+    return upload_sims(b);
+}
+
+int vfp_haissinski(vfp_sim *sim, int32_t iters, double alpha) { return vfp_batch_haissinski(sim, 0, iters, alpha); }
+
 int vfp_batch_seed(vfp_batch *b, int32_t dst, int32_t src)
 {
     if (!b || dst < 0 || src < 0 || dst >= b->count || src >= b->count || dst == src)

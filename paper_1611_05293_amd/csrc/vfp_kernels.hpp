@@ -783,6 +783,70 @@ __global__ __launch_bounds__(kThreads) void spectrum_kernel(const SimDev *__rest
     }
 }
 
+// Haissinski starting distribution (Appendix A): rho ~ exp(-q^2/2 - U),
+// U' = V[rho], dq*sum(rho) = Q0, solved by the damped fixed-point iteration
+// rho <- (1-alpha) rho + alpha F(rho) from the Gaussian, U by the cumulative
+// trapezoid rule from q_min; psi_ij = rho_i g_j with the unit Gaussian g in p
+// normalised on the grid.  One workgroup; dynamic LDS: 3n doubles.
+template <typename T>
+__global__ __launch_bounds__(kThreads) void haissinski_kernel(const SimDev *__restrict__ sims, int which, int buf,
+                                                              int iters, double alpha)
+{
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    __shared__ double red[kThreads];
+    const SimDev &sd = sims[which];
+    const int n = sd.n, tid = threadIdx.x;
+    double *rho = (double *)smem_raw, *V = rho + n, *F = V + n;
+    double part = 0.0;
+    for (int i = tid; i < n; i += kThreads) {
+        const double q = sd.q_min + i * sd.dq;
+        rho[i] = exp(-0.5 * q * q);
+        part += rho[i];
+    }
+    double tot = block_sum(part, red);
+    for (int i = tid; i < n; i += kThreads) rho[i] *= sd.Q0 / (sd.dq * tot);
+    __syncthreads();
+    for (int it = 0; it < iters; ++it) {
+        for (int i = tid; i < n; i += kThreads) {
+            double v = 0.0;
+            if (sd.has_wake)
+                for (int j = 0; j < n; ++j) v += sd.wl64[i - j + n - 1] * rho[j];
+            V[i] = sd.S * v;
+        }
+        __syncthreads();
+        if (tid == 0) {                      // cumulative trapezoid, in order
+            double u = 0.0;
+            F[0] = 0.0;
+            for (int i = 1; i < n; ++i) {
+                u += 0.5 * (V[i - 1] + V[i]) * sd.dq;
+                F[i] = u;
+            }
+        }
+        __syncthreads();
+        part = 0.0;
+        for (int i = tid; i < n; i += kThreads) {
+            const double q = sd.q_min + i * sd.dq;
+            F[i] = exp(-0.5 * q * q - F[i]);
+            part += F[i];
+        }
+        tot = block_sum(part, red);
+        for (int i = tid; i < n; i += kThreads) rho[i] = (1.0 - alpha) * rho[i] + alpha * F[i] * (sd.Q0 / (sd.dq * tot));
+        __syncthreads();
+    }
+    part = 0.0;
+    for (int j = tid; j < n; j += kThreads) {
+        const double p = sd.p_min + j * sd.dp;
+        part += exp(-0.5 * p * p);
+    }
+    const double G = block_sum(part, red);
+    T *out = (T *)sd.psi[buf];
+    for (int i = 0; i < n; ++i)
+        for (int j = tid; j < n; j += kThreads) {
+            const double p = sd.p_min + j * sd.dp;
+            out[(size_t)i * n + j] = (T)(rho[i] * exp(-0.5 * p * p) / (sd.dp * G));
+        }
+}
+
 // Q0 = dq * dp * sum psi0 of the FP64 input, before any conversion to the
 // storage type (one workgroup, fixed summation order)
 __global__ __launch_bounds__(kThreads) void charge64_kernel(const double *__restrict__ psi, size_t nn, double dqdp,

@@ -100,6 +100,8 @@ def load():
             "vfp_batch_csr_spectrum": (C.c_int, [h, C.c_int32, _dp]),
             "vfp_csr_spectrum": (C.c_int, [h, _dp]),
             "vfp_batch_seed": (C.c_int, [h, C.c_int32, C.c_int32]),
+            "vfp_batch_haissinski": (C.c_int, [h, C.c_int32, C.c_int32, C.c_double]),
+            "vfp_haissinski": (C.c_int, [h, C.c_int32, C.c_double]),
             "vfp_batch_kernel_times": (C.c_int, [h, _dp]),
         }
         for name, (res, args) in sig.items():
@@ -256,6 +258,9 @@ class Batch:
         _check(load().vfp_batch_csr_spectrum(self._h, i, _ptr(out)))
         return out
 
+    def haissinski(self, i: int, iters: int = 200, alpha: float = 0.5):
+        _check(load().vfp_batch_haissinski(self._h, int(i), int(iters), float(alpha)))
+
     def seed(self, dst: int, src: int):
         _check(load().vfp_batch_seed(self._h, int(dst), int(src)))
 
@@ -325,6 +330,9 @@ class Sim:
         out = np.zeros(self.M // 2 + 1)
         _check(load().vfp_csr_spectrum(self._h, _ptr(out)))
         return out
+
+    def haissinski(self, iters: int = 200, alpha: float = 0.5):
+        _check(load().vfp_haissinski(self._h, int(iters), float(alpha)))
 
     def get_psi(self) -> np.ndarray:
         out = np.zeros((self.n, self.n))

@@ -141,3 +141,22 @@ def test_seed_chains_a_current_scan():
     zr, zi = lo_I.impedance()
     ref, _ = oracle.run(p, oracle.wake_kernel(zr, zi, 96), ref_hi, 15, Q0)
     assert rel_l1(b.get_psi(1), ref) <= 1e-12
+
+
+def test_haissinski_start_matches_oracle():
+    import oracle
+    from paper_1611_05293_amd import inputs
+    n, pad = 64, 2
+    sim = inputs.Sim(n, -6, 6, -6, 6, 150, 0.08, 4, z_scale=3.0, Pi=0.5)
+    p = oracle.OracleParams.from_recipe(sim)
+    zr, zi = sim.impedance()
+    w = oracle.wake_kernel(zr, zi, n * pad)
+    ref = oracle.haissinski(p, w, 200, 0.5, 1.0)
+    b = vfp.Batch([vfp.sim_kwargs(sim, precision="fp64"), vfp.sim_kwargs(sim, precision="fp64")])
+    b.haissinski(0, 200, 0.5)
+    assert b.steps_done(0) == 0
+    assert rel_l1(b.get_psi(0), ref) <= 1e-12
+    # and it is the equilibrium: the step map moves it far less than the Gaussian start of sim 1
+    h0, g0 = b.profile(0), b.profile(1)
+    b.step(450)
+    assert np.abs(b.profile(0) - h0).max() < 0.1 * np.abs(b.profile(1) - g0).max()

@@ -394,3 +394,33 @@ def test_csr_spectrum_matches_fft_and_sums_to_power():
     assert np.allclose(spec, S / M * mult * zr * np.abs(rt) ** 2, rtol=1e-12, atol=1e-15)
     w = oracle.wake_kernel(zr, zi, M)
     assert abs(spec.sum() - oracle.csr_power(p, w, psi)) < 1e-12 * abs(spec.sum())
+
+
+def test_haissinski_solver_is_self_consistent_and_stationary():
+    """Appendix A: the Haissinski distribution is the equilibrium below
+    threshold.  The solved profile satisfies its defining equation and the
+    oracle's own step map leaves it (nearly) unchanged -- far closer than a
+    Gaussian start -- with a unit energy spread."""
+    from paper_1611_05293_amd import inputs
+    n, pad = 64, 2
+    zr, zi = inputs.impedance_samples(n, pad, -6, 6, "parallel_plate", 0.5)
+    p = OracleParams(n=n, q_min=-6, q_max=6, p_min=-6, p_max=6, steps_per_period=150, beta=0.08,
+                     interp=4, padding=pad, z_scale=3.0)
+    w = oracle.wake_kernel(zr, zi)
+    h = oracle.haissinski(p, w, 200, 0.5)
+    qg = np.linspace(-6, 6, n)
+    dq = qg[1] - qg[0]
+    rho = oracle.profile(p, h)
+    assert abs(dq * rho.sum() - 1.0) < 1e-12
+    V = oracle.wake(p, w, rho)
+    U = np.concatenate([[0.0], np.cumsum(0.5 * (V[1:] + V[:-1]) * dq)])
+    F = np.exp(-qg ** 2 / 2 - U)
+    F /= dq * F.sum()
+    assert np.abs(rho - F).max() < 1e-10 * rho.max()           # fixed point reached
+    out, _ = oracle.run(p, w, h, 150 * 3, 1.0)
+    g = inputs.gaussian_psi(n, -6, 6, -6, 6)
+    outg, _ = oracle.run(p, w, g, 150 * 3, 1.0)
+    moved_h = np.abs(oracle.profile(p, out) - rho).max()
+    moved_g = np.abs(oracle.profile(p, outg) - oracle.profile(p, g)).max()
+    assert moved_h < 0.1 * moved_g
+    assert abs(oracle.moments(p, h)[4] - 1.0) < 1e-3
