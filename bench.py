@@ -139,6 +139,8 @@ def main():
     ap.add_argument("--plain-steps", type=int, default=20)
     ap.add_argument("--autotune", action="store_true")
     ap.add_argument("--no-forms", action="store_true", help="skip the FP32 and Manhattan forms")
+    ap.add_argument("--staged", type=int, default=None, help="FP32 step kernel layout: 0 generic, 1, 2")
+    ap.add_argument("--cells", type=int, default=0, help="cells per work unit (0: built-in)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
@@ -156,6 +158,8 @@ def main():
     with torch.cuda.stream(stream):
         b = vfp.Batch([vfp.sim_kwargs(s, precision=prec) for s in sims], stream=stream, torch_workspace=True)
     log("created batch")
+    if args.staged is not None or args.cells:
+        b.set_tuning(args.cells, True, 1 if args.staged is None else args.staged)
     tuned = None
     if args.autotune:
         tuned = b.autotune(ticks=10)
@@ -186,6 +190,8 @@ def main():
                 continue
             fb = vfp.Batch([vfp.sim_kwargs(s_, precision=fprec, rotation=rot) for s_ in sims], stream=stream,
                            torch_workspace=True)
+            if args.staged is not None or args.cells:
+                fb.set_tuning(args.cells, True, 1 if args.staged is None else args.staged)
             fb.step(min(args.warmup, 20))
             fr = timed(fb, stream, cells_tick, 8 if fprec == "fp64" else 4, args.steps)
             forms[name] = {"value": fr["value"], "ms_per_step": fr["ms"] / args.steps,
@@ -241,7 +247,7 @@ def main():
                    "wake": {"fp16": "FP16 hi/lo MFMA", "bf16": "BF16 hi/lo MFMA",
                             "fp32": "FP32 VALU", "fp64": "FP64 VALU"}[prec],
                    "sims": len(sims), "cells_per_tick": cells_tick,
-                   "cells_per_unit": tuned},
+                   "cells_per_unit": tuned or args.cells or None, "kernel_layout": args.staged},
         "parity": None if err is None else {"max_rel_l1_vs_fp64_oracle": err, "after_steps": args.warmup,
                                             "sims_checked": "one per grid size"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",

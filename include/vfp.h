@@ -178,9 +178,12 @@ void vfp_batch_destroy(vfp_batch *b);
 
 /* Launch tuning: columns per work unit are chosen per grid size.  cells is
  * the number of phase-space cells one workgroup owns (0 restores the
- * built-in choice); use_graph = 0 launches every tick directly; staged = 0
- * keeps the generic step kernel even where the LDS-staged FP32 kernel
- * applies (same arithmetic definition, different evaluation order). */
+ * built-in choice); use_graph = 0 launches every tick directly; staged
+ * selects the FP32 step kernel where a staged one applies: 0 the generic
+ * kernel, 1 the staged kernel with 64-row chunks and separate kick and
+ * damping passes, 2 the staged kernel with 256-row chunks and the kick merged
+ * into the damping pass (same arithmetic definition, different evaluation
+ * order). */
 int vfp_batch_set_tuning(vfp_batch *b, int32_t cells_per_unit, int32_t use_graph, int32_t staged);
 
 /* CSR spectrum of simulation i's current state (Sec. IV.C, P(t,k) ~ Re Z_k

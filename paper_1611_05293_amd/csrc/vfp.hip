@@ -20,6 +20,7 @@
 #include "vfp.h"
 #include "vfp_kernels.hpp"
 #include "vfp_step32.hpp"
+#include "vfp_step32b.hpp"
 
 using namespace vfp;
 
@@ -187,7 +188,7 @@ struct vfp_batch {
     size_t stage_elems = 0;
     size_t lds_step = 0, lds_stats = 0, lds_wake = 0;
     bool fast = false;             // all active simulations use the FP32 staged kernel
-    bool allow_staged = true;      // tuning: the staged kernel may be used
+    int staged = 1;                // tuning: 0 generic kernel, 1 / 2 the staged FP32 layouts
     std::vector<WakeTile> wtiles;
     WakeTile *d_wtiles = nullptr;
     size_t wtiles_cap = 0;
@@ -231,8 +232,9 @@ int rebuild_units(vfp_batch *b)
         const int n = b->hs[s].p.n;
         const int w = choose_strip(n, b->cells);
         const int o0 = (b->K - 1) / 2;
+        const int SY = b->staged == 2 ? (n >= 256 ? 256 : (n + 63) / 64 * 64) + 2 * kH : kSY;
         for (int i0 = 0; i0 < n; i0 += w)
-            b->units.push_back(Unit{s, i0, std::min(w, n - i0), (kH - o0) * (kSY + 1)});
+            b->units.push_back(Unit{s, i0, std::min(w, n - i0), (kH - o0) * (SY + 1)});
     }
     if (b->units.size() > b->units_cap) {
         if (b->d_units) HIPCHK(hipFree(b->d_units));
@@ -246,14 +248,21 @@ int rebuild_units(vfp_batch *b)
     if (!b->active.empty()) rc = upload(b->d_active, b->active.data(), sizeof(int) * b->active.size(), b->stream);
     if (rc) return rc;
     // kernel choice and LDS of the fused step
-    b->fast = b->allow_staged && b->precision != VFP_FP64 && !b->active.empty();
+    b->fast = b->staged > 0 && b->precision != VFP_FP64 && !b->active.empty();
     for (int s : b->active) b->fast = b->fast && b->hs[s].fast;
     size_t mx = 0;
     for (const Unit &u : b->units) {
         const size_t n = b->hs[u.sim].p.n;
-        const size_t bytes = b->fast ? (2 * (size_t)u.w * (n + 2 * kPad) + (size_t)(u.w + 2 * kH) * kSY +
-                                        (b->rotation ? (size_t)u.w * kSY : 0)) * 4
-                                     : 2 * (size_t)u.w * n * elem_size(b->precision);
+        size_t bytes;
+        if (!b->fast) {
+            bytes = 2 * (size_t)u.w * n * elem_size(b->precision);
+        } else if (b->staged == 1) {
+            bytes = (2 * (size_t)u.w * (n + 2 * kPad) + (size_t)(u.w + 2 * kH) * kSY +
+                     (b->rotation ? (size_t)u.w * kSY : 0)) * 4;
+        } else {
+            const size_t SY = (n >= 256 ? 256 : (n + 63) / 64 * 64) + 2 * kH;
+            bytes = ((size_t)u.w * (n + 2 * kPad) + (size_t)(u.w + 2 * kH) * SY + (b->rotation ? (size_t)u.w * SY : 0)) * 4;
+        }
         mx = std::max(mx, bytes);
     }
     b->lds_step = mx;
@@ -304,9 +313,9 @@ void launch_step_t(vfp_batch *b, int parity)
 template <int K, int WAKE, bool CL, int ROT>
 void launch_step32_t(vfp_batch *b, int parity)
 {
-    auto k = step32_kernel<K, WAKE, CL, ROT>;
-    static int cur = 0;
-    lds_limit(k, b->lds_step, cur);
+    auto k = b->staged == 2 ? step32b_kernel<K, WAKE, CL, ROT> : step32_kernel<K, WAKE, CL, ROT>;
+    static int cur_a = 0, cur_b = 0;
+    lds_limit(k, b->lds_step, b->staged == 2 ? cur_b : cur_a);
     hipLaunchKernelGGL(k, dim3((unsigned)b->units.size()), dim3(kThreads), b->lds_step, b->stream,
                        b->d_sd, b->d_units, (int)b->units.size(), parity);
 }
@@ -1089,7 +1098,8 @@ int vfp_batch_set_tuning(vfp_batch *b, int32_t cells_per_unit, int32_t use_graph
     HIPCHK(hipStreamSynchronize(b->stream));
     b->cells = cells;
     b->use_graph = use_graph != 0;
-    b->allow_staged = staged != 0;
+    if (staged < 0 || staged > 2) return fail(VFP_EINVAL, "staged must be 0, 1 or 2");
+    b->staged = staged;
     b->units_dirty = true;
     b->graph_valid = false;
     return VFP_OK;

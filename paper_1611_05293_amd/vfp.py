@@ -244,9 +244,8 @@ class Batch:
         _check(load().vfp_batch_steps_done(self._h, i, C.byref(v)))
         return v.value
 
-    def set_tuning(self, cells_per_unit: int = 0, use_graph: bool = True, staged: bool = True):
-        _check(load().vfp_batch_set_tuning(self._h, int(cells_per_unit), int(bool(use_graph)),
-                                           int(bool(staged))))
+    def set_tuning(self, cells_per_unit: int = 0, use_graph: bool = True, staged: int = 1):
+        _check(load().vfp_batch_set_tuning(self._h, int(cells_per_unit), int(bool(use_graph)), int(staged)))
 
     def autotune(self, ticks: int = 20) -> int:
         c = C.c_int32()

@@ -160,3 +160,21 @@ def test_haissinski_start_matches_oracle():
     h0, g0 = b.profile(0), b.profile(1)
     b.step(450)
     assert np.abs(b.profile(0) - h0).max() < 0.1 * np.abs(b.profile(1) - g0).max()
+
+
+@pytest.mark.parametrize("staged", [0, 1, 2])
+@pytest.mark.parametrize("rotation", [0, 1])
+@pytest.mark.parametrize("clamp", [0, 1])
+def test_kernel_variants_match_oracle(staged, rotation, clamp):
+    """Every FP32 kernel layout (generic, staged 64-row chunks, staged 256-row
+    chunks with the merged kick) and both rotations against the oracle."""
+    sims = mixed_sims()
+    for s in sims:
+        s.rotation, s.clamp = rotation, clamp
+    b = vfp.Batch([vfp.sim_kwargs(s, precision="fp32") for s in sims])
+    b.set_tuning(0, True, staged)
+    b.step(30)
+    for i, s in enumerate(sims):
+        ref, _, _, _ = oracle_run(s, 30)
+        err = rel_l1(b.get_psi(i), ref)
+        assert err <= 1e-5, (i, s.n, err)
