@@ -162,8 +162,9 @@ def main():
         b.set_tuning(args.cells, True, 1 if args.staged is None else args.staged)
     tuned = None
     if args.autotune:
-        tuned = b.autotune(ticks=10)
-        log(f"autotuned cells per unit: {tuned}")
+        tuned, layout = b.autotune(ticks=10)
+        args.staged = layout
+        log(f"autotuned: {tuned} cells per unit, kernel layout {layout}")
     b.step(args.warmup)
     torch.cuda.synchronize()
     log(f"warmup {args.warmup} ticks done")

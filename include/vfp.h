@@ -226,10 +226,15 @@ int vfp_batch_last_wake(vfp_batch *b, int32_t i, double *V);
 int vfp_batch_kernel_timing(vfp_batch *b, int32_t enable);
 int vfp_batch_kernel_times(vfp_batch *b, double out[4]);
 
-/* Autotuner: times `ticks` ticks for each candidate tile size with HIP
- * events on the batch's stream, keeps the fastest, and returns the chosen
- * cells per unit.  The state is saved and restored around the trials. */
-int vfp_batch_autotune(vfp_batch *b, int32_t ticks, int32_t *chosen_cells);
+/* Autotuner: times `ticks` ticks for every candidate (cells per unit in
+ * {2048, 4096, 8192, 16384} and, for FP32 storage, the staged layouts 1 and
+ * 2) with HIP events on the batch's stream, keeps the fastest and returns
+ * it.  The state is saved and restored around the trials. */
+int vfp_batch_autotune(vfp_batch *b, int32_t ticks, int32_t *chosen_cells, int32_t *chosen_staged);
+
+/* Architecture name of the current device (e.g. "gfx950:sramecc+:xnack-"),
+ * the key of autotuning caches. */
+int vfp_device_arch(char *name, int32_t len);
 
 #ifdef __cplusplus
 }

@@ -1240,7 +1240,7 @@ int vfp_batch_kernel_times(vfp_batch *b, double out[4])
     return VFP_OK;
 }
 
-int vfp_batch_autotune(vfp_batch *b, int32_t ticks, int32_t *chosen_cells)
+int vfp_batch_autotune(vfp_batch *b, int32_t ticks, int32_t *chosen_cells, int32_t *chosen_staged)
 {
     if (!b || ticks < 1) return fail(VFP_EINVAL, "invalid arguments");
     HIPCHK(hipStreamSynchronize(b->stream));
@@ -1260,33 +1260,37 @@ int vfp_batch_autotune(vfp_batch *b, int32_t ticks, int32_t *chosen_cells)
     const int parity0 = b->parity;
     const int every0 = b->every;
     const bool timing0 = b->timing;
+    const int staged0 = b->staged, cells0 = b->cells;
     b->every = 0;   // no records during trials
     b->timing = false;
-    std::vector<int> cand = b->precision == VFP_FP64 ? std::vector<int>{1024, 2048, 4096, 8192}
-                                                     : std::vector<int>{2048, 4096, 8192, 16384};
+    std::vector<int> layouts = b->precision == VFP_FP64 ? std::vector<int>{0} : std::vector<int>{1, 2};
+    std::vector<int> cand = {2048, 4096, 8192, 16384};
     hipEvent_t e0, e1;
     HIPCHK(hipEventCreate(&e0));
     HIPCHK(hipEventCreate(&e1));
     float best = 1e30f;
-    int best_c = b->cells;
+    int best_c = cells0, best_l = staged0;
     int rc = VFP_OK;
-    for (int c : cand) {
-        if (c * es * 2 > 128 * 1024) continue;
-        b->cells = c;
-        b->units_dirty = true;
-        rc = rebuild_units(b);
-        if (rc == VFP_EINVAL) { rc = VFP_OK; continue; }   // does not fit the LDS
+    for (int layout : layouts) {
+        for (int c : cand) {
+            b->cells = c;
+            b->staged = layout;
+            b->units_dirty = true;
+            rc = rebuild_units(b);
+            if (rc == VFP_EINVAL) { rc = VFP_OK; continue; }   // does not fit the LDS
+            if (rc) break;
+            // warm up, then time
+            for (int t = 0; t < 2 && rc == VFP_OK; ++t) { rc = launch_tick(b, b->parity); b->parity ^= 1; }
+            if (rc) break;
+            HIPCHK(hipEventRecord(e0, b->stream));
+            for (int t = 0; t < ticks && rc == VFP_OK; ++t) { rc = launch_tick(b, b->parity); b->parity ^= 1; }
+            HIPCHK(hipEventRecord(e1, b->stream));
+            HIPCHK(hipEventSynchronize(e1));
+            float ms = 0.0f;
+            HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+            if (ms < best) { best = ms; best_c = c; best_l = layout; }
+        }
         if (rc) break;
-        // warm up, then time
-        for (int t = 0; t < 2 && rc == VFP_OK; ++t) { rc = launch_tick(b, b->parity); b->parity ^= 1; }
-        if (rc) break;
-        HIPCHK(hipEventRecord(e0, b->stream));
-        for (int t = 0; t < ticks && rc == VFP_OK; ++t) { rc = launch_tick(b, b->parity); b->parity ^= 1; }
-        HIPCHK(hipEventRecord(e1, b->stream));
-        HIPCHK(hipEventSynchronize(e1));
-        float ms = 0.0f;
-        HIPCHK(hipEventElapsedTime(&ms, e0, e1));
-        if (ms < best) { best = ms; best_c = c; }
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
@@ -1303,11 +1307,24 @@ int vfp_batch_autotune(vfp_batch *b, int32_t ticks, int32_t *chosen_cells)
     b->parity = parity0;
     b->every = every0;
     b->timing = timing0;
-    if (rc) return rc;
-    b->cells = best_c;
+    b->cells = rc ? cells0 : best_c;
+    b->staged = rc ? staged0 : best_l;
     b->units_dirty = true;
     b->graph_valid = false;
+    if (rc) return rc;
     if (chosen_cells) *chosen_cells = best_c;
+    if (chosen_staged) *chosen_staged = best_l;
+    return VFP_OK;
+}
+
+int vfp_device_arch(char *name, int32_t len)
+{
+    if (!name || len < 1) return fail(VFP_EINVAL, "invalid arguments");
+    int dev = 0;
+    HIPCHK(hipGetDevice(&dev));
+    hipDeviceProp_t prop;
+    HIPCHK(hipGetDeviceProperties(&prop, dev));
+    std::snprintf(name, (size_t)len, "%s", prop.gcnArchName);
     return VFP_OK;
 }
 

@@ -94,7 +94,8 @@ def load():
             "vfp_batch_steps_done": (C.c_int, [h, C.c_int32, C.POINTER(C.c_int64)]),
             "vfp_batch_destroy": (None, [h]),
             "vfp_batch_set_tuning": (C.c_int, [h, C.c_int32, C.c_int32, C.c_int32]),
-            "vfp_batch_autotune": (C.c_int, [h, C.c_int32, C.POINTER(C.c_int32)]),
+            "vfp_batch_autotune": (C.c_int, [h, C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]),
+            "vfp_device_arch": (C.c_int, [C.c_char_p, C.c_int32]),
             "vfp_batch_kernel_timing": (C.c_int, [h, C.c_int32]),
             "vfp_batch_last_wake": (C.c_int, [h, C.c_int32, _dp]),
             "vfp_batch_csr_spectrum": (C.c_int, [h, C.c_int32, _dp]),
@@ -189,6 +190,7 @@ class Batch:
         arr = (Params * len(ps))(*ps)
         self.count = len(ps)
         self.n = [p.n for p in ps]
+        self._key = (ps[0].interp, ps[0].precision, ps[0].rotation, ps[0].clamp)
         self.M = [p.n * p.padding for p in ps]
         self._ws = None
         ws_ptr, ws_bytes = None, 0
@@ -247,10 +249,38 @@ class Batch:
     def set_tuning(self, cells_per_unit: int = 0, use_graph: bool = True, staged: int = 1):
         _check(load().vfp_batch_set_tuning(self._h, int(cells_per_unit), int(bool(use_graph)), int(staged)))
 
-    def autotune(self, ticks: int = 20) -> int:
-        c = C.c_int32()
-        _check(load().vfp_batch_autotune(self._h, int(ticks), C.byref(c)))
-        return c.value
+    def autotune(self, ticks: int = 20, cache: Optional[str] = None) -> tuple:
+        """Pick cells per unit and kernel layout by timing (vfp_batch_autotune).
+        With `cache` (a JSON file), a previous choice for the same device,
+        grid-size mix, interpolation, precision and rotation is reused and new
+        choices are stored.  Returns (cells, layout)."""
+        key = None
+        if cache:
+            import json
+            buf = C.create_string_buffer(128)
+            _check(load().vfp_device_arch(buf, 128))
+            key = "|".join([buf.value.decode(), ",".join(f"{n}x{k}" for n, k in sorted(
+                {n: self.n.count(n) for n in self.n}.items())), str(self._key)])
+            table = {}
+            if os.path.exists(cache):
+                with open(cache) as f:
+                    table = json.load(f)
+            if key in table:
+                cells, layout = table[key]
+                self.set_tuning(cells, True, layout)
+                return int(cells), int(layout)
+        c, l = C.c_int32(), C.c_int32()
+        _check(load().vfp_batch_autotune(self._h, int(ticks), C.byref(c), C.byref(l)))
+        if cache:
+            import json
+            table = {}
+            if os.path.exists(cache):
+                with open(cache) as f:
+                    table = json.load(f)
+            table[key] = [c.value, l.value]
+            with open(cache, "w") as f:
+                json.dump(table, f, indent=1, sort_keys=True)
+        return c.value, l.value
 
     def csr_spectrum(self, i: int) -> np.ndarray:
         out = np.zeros(self.M[i] // 2 + 1)

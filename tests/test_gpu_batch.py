@@ -69,8 +69,8 @@ def test_autotune_preserves_state_and_results():
     sims = mixed_sims()
     b = vfp.Batch([vfp.sim_kwargs(s, precision="fp32") for s in sims])
     b.step(5)
-    cells = b.autotune(ticks=4)
-    assert cells in (2048, 4096, 8192, 16384)
+    cells, layout = b.autotune(ticks=4)
+    assert cells in (2048, 4096, 8192, 16384) and layout in (1, 2)
     assert all(b.steps_done(i) == 5 for i in range(len(sims)))
     b.step(15)
     for i, s in enumerate(sims):
@@ -178,3 +178,14 @@ def test_kernel_variants_match_oracle(staged, rotation, clamp):
         ref, _, _, _ = oracle_run(s, 30)
         err = rel_l1(b.get_psi(i), ref)
         assert err <= 1e-5, (i, s.n, err)
+
+
+def test_autotune_cache_roundtrip(tmp_path):
+    sims = mixed_sims()[:2]
+    cache = str(tmp_path / "tune.json")
+    a = vfp.Batch([vfp.sim_kwargs(s, precision="fp32") for s in sims])
+    first = a.autotune(ticks=2, cache=cache)
+    b = vfp.Batch([vfp.sim_kwargs(s, precision="fp32") for s in sims])
+    assert b.autotune(ticks=2, cache=cache) == first          # served from the cache
+    import json
+    assert len(json.load(open(cache))) == 1
