@@ -141,6 +141,8 @@ def main():
     ap.add_argument("--no-forms", action="store_true", help="skip the FP32 and Manhattan forms")
     ap.add_argument("--staged", type=int, default=None, help="FP32 step kernel layout: 0 generic, 1, 2")
     ap.add_argument("--cells", type=int, default=0, help="cells per work unit (0: built-in)")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain 512 MiB device copy 5 times (scale of the HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
@@ -148,6 +150,17 @@ def main():
 
     import torch                          # device memory and the stream only
     from paper_1611_05293_amd import vfp
+
+    if args.copy_calibration:
+        a = torch.empty(512 << 20, dtype=torch.uint8, device="cuda")
+        c = torch.empty_like(a)
+        a.fill_(1)
+        torch.cuda.synchronize()
+        for _ in range(5):
+            c.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_per_launch": 512 << 20, "launches": 5}), flush=True)
+        return
 
     sims, prec, desc = workload(args.workload)
     prec = args.precision or prec
