@@ -21,6 +21,10 @@ sys.path.insert(0, ROOT)
 
 METRIC = "phase-space cell-updates/s (N²·steps·sims/s), batched vs plain, at stated L1 err"
 HBM_PEAK_GBS = 8000.0
+# step kernel of each layout (0: generic kernel, also the FP64 path)
+STEP_KERNEL = {0: "vfp::step_kernel", 1: "vfp::step32_kernel", 2: "vfp::step32b_kernel", 3: "vfp::step32c_kernel"}
+TRAFFIC_FILE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles",
+                            "step_kernel_hbm_traffic_scan200_fp16.json")
 
 
 def log(msg):
@@ -139,11 +143,25 @@ def main():
     ap.add_argument("--plain-steps", type=int, default=20)
     ap.add_argument("--autotune", action="store_true")
     ap.add_argument("--no-forms", action="store_true", help="skip the FP32 and Manhattan forms")
-    ap.add_argument("--staged", type=int, default=None, help="FP32 step kernel layout: 0 generic, 1, 2")
+    ap.add_argument("--staged", type=int, default=None, help="FP32 step kernel layout: 0 generic, 1, 2, 3")
     ap.add_argument("--cells", type=int, default=0, help="cells per work unit (0: built-in)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 512 MiB device copy 5 times (scale of the HBM byte counters)")
+    ap.add_argument("--counter-summary", nargs=4, metavar=("FETCH", "WRITE", "COPY_FETCH", "COPY_WRITE"),
+                    help="write the step kernel's HBM bytes per launch from four rocprofv3 --pmc output "
+                         "folders (no GPU needed) and exit")
+    ap.add_argument("--layout-for-summary", type=int, default=3)
     args = ap.parse_args()
+    if args.counter_summary:
+        from paper_1611_05293_amd import inputs, profiles
+        sims = inputs.config(5)
+        alg = 8 * sum(s_.n * s_.n for s_ in sims)
+        d = profiles.summarize(*args.counter_summary, kernel_prefix=STEP_KERNEL[args.layout_for_summary],
+                               copy_bytes=512 << 20, algorithmic_bytes=alg)
+        with open(TRAFFIC_FILE, "w") as fh:
+            json.dump(d, fh, indent=1)
+        print(json.dumps(d))
+        return
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
         sys.exit(2)
@@ -172,12 +190,12 @@ def main():
         b = vfp.Batch([vfp.sim_kwargs(s, precision=prec) for s in sims], stream=stream, torch_workspace=True)
     log("created batch")
     if args.staged is not None or args.cells:
-        b.set_tuning(args.cells, True, 1 if args.staged is None else args.staged)
+        b.set_tuning(args.cells, True, b.get_tuning()[2] if args.staged is None else args.staged)
     tuned = None
     if args.autotune:
         tuned, layout = b.autotune(ticks=10)
-        args.staged = layout
         log(f"autotuned: {tuned} cells per unit, kernel layout {layout}")
+    cells_unit, _, args.staged = b.get_tuning()
     b.step(args.warmup)
     torch.cuda.synchronize()
     log(f"warmup {args.warmup} ticks done")
@@ -204,8 +222,7 @@ def main():
                 continue
             fb = vfp.Batch([vfp.sim_kwargs(s_, precision=fprec, rotation=rot) for s_ in sims], stream=stream,
                            torch_workspace=True)
-            if args.staged is not None or args.cells:
-                fb.set_tuning(args.cells, True, 1 if args.staged is None else args.staged)
+            fb.set_tuning(cells_unit, True, args.staged)
             fb.step(min(args.warmup, 20))
             fr = timed(fb, stream, cells_tick, 8 if fprec == "fp64" else 4, args.steps)
             forms[name] = {"value": fr["value"], "ms_per_step": fr["ms"] / args.steps,
@@ -244,6 +261,13 @@ def main():
         cpu = cpu_baseline(sims, args.cpu_seconds)
         log(f"oracle: {cpu['value']:.3e} cell-updates/s on {cpu['cores']} threads")
 
+    # HBM bytes per launch from the stored counter summary, only while it was
+    # taken on the current kernel sources (and only for the workload it covers)
+    kname = STEP_KERNEL[args.staged if prec != "fp64" else 0]
+    traffic = None
+    if args.workload == "scan200" and prec == "fp16":
+        from paper_1611_05293_amd import profiles
+        traffic = profiles.traffic_for_current_sources(TRAFFIC_FILE, kname)
     out = {
         "metric": METRIC,
         "value": value,
@@ -261,12 +285,12 @@ def main():
                    "wake": {"fp16": "FP16 hi/lo MFMA", "bf16": "BF16 hi/lo MFMA",
                             "fp32": "FP32 VALU", "fp64": "FP64 VALU"}[prec],
                    "sims": len(sims), "cells_per_tick": cells_tick,
-                   "cells_per_unit": tuned or args.cells or None, "kernel_layout": args.staged},
+                   "cells_per_unit": cells_unit, "kernel_layout": args.staged},
         "parity": None if err is None else {"max_rel_l1_vs_fp64_oracle": err, "after_steps": args.warmup,
                                             "sims_checked": "one per grid size"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": "step_kernel", "avg_launch_us": step_avg_ms * 1e3,
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "kernel": kname, "avg_launch_us": step_avg_ms * 1e3,
                      "bytes_per_launch": bytes_launch, "wake_kernel_avg_us": wake_avg_ms * 1e3},
         "forms": forms,
         "plain": plain,

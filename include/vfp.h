@@ -182,9 +182,15 @@ void vfp_batch_destroy(vfp_batch *b);
  * selects the FP32 step kernel where a staged one applies: 0 the generic
  * kernel, 1 the staged kernel with 64-row chunks and separate kick and
  * damping passes, 2 the staged kernel with 256-row chunks and the kick merged
- * into the damping pass (same arithmetic definition, different evaluation
- * order). */
+ * into the damping pass, 3 the staged kernel with 192-row chunks, 16-byte
+ * staging, FP32 source displacements and per-row damping coefficients
+ * (same arithmetic definition, different evaluation order; returns
+ * VFP_EINVAL for other values). */
 int vfp_batch_set_tuning(vfp_batch *b, int32_t cells_per_unit, int32_t use_graph, int32_t staged);
+
+/* The tuning in force: cells per unit, graph replay on/off, kernel layout
+ * (any output pointer may be NULL). */
+int vfp_batch_get_tuning(vfp_batch *b, int32_t *cells_per_unit, int32_t *use_graph, int32_t *staged);
 
 /* CSR spectrum of simulation i's current state (Sec. IV.C, P(t,k) ~ Re Z_k
  * |rho~(k,t)|^2): out[k], k = 0..M/2 (floor(M/2)+1 values, FP64), with
@@ -227,8 +233,8 @@ int vfp_batch_kernel_timing(vfp_batch *b, int32_t enable);
 int vfp_batch_kernel_times(vfp_batch *b, double out[4]);
 
 /* Autotuner: times `ticks` ticks for every candidate (cells per unit in
- * {2048, 4096, 8192, 16384} and, for FP32 storage, the staged layouts 1 and
- * 2) with HIP events on the batch's stream, keeps the fastest and returns
+ * {2048, 4096, 8192, 16384} and, for FP32 storage, the staged layouts 1, 2
+ * and 3) with HIP events on the batch's stream, keeps the fastest and returns
  * it.  The state is saved and restored around the trials. */
 int vfp_batch_autotune(vfp_batch *b, int32_t ticks, int32_t *chosen_cells, int32_t *chosen_staged);
 

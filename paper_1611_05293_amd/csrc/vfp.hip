@@ -21,6 +21,7 @@
 #include "vfp_kernels.hpp"
 #include "vfp_step32.hpp"
 #include "vfp_step32b.hpp"
+#include "vfp_step32c.hpp"
 
 using namespace vfp;
 
@@ -74,6 +75,28 @@ int choose_strip(int n, int cells)
     w = std::max(1, std::min(w, std::min(n, kMaxStrip)));
     return w;
 }
+
+// Strip width of the chunked staged layout: at most kMaxStripC columns, the
+// per-(column, 256-row block) partial sums fit the workgroup's reduction
+// array, and a grid with more than one chunk keeps every staged column of a
+// wave in the prefetch registers.
+// The dynamic LDS of a unit stays under kLdsBudgetC so that five workgroups
+// fit on a compute unit.
+constexpr size_t kLdsBudgetC = 28 * 1024;
+size_t lds_bytes_c(int n, int w, int rotation)
+{
+    return ((size_t)w * (n + 2 * kPad) + (size_t)(w + 2 * kH) * kSYC + (rotation ? (size_t)w * kSYC : 0)) * 4;
+}
+int choose_strip_c(int n, int cells, int rotation)
+{
+    int w = std::max(1, std::min(cells / n, std::min(n, kMaxStripC)));
+    const int nb = (n + 255) / 256;
+    w = std::min(w, kThreads / nb);
+    if (n > kCH) w = std::min(w, kWaves * kPF4 - 2 * kH);
+    while (w > 1 && lds_bytes_c(n, w, rotation) > kLdsBudgetC) --w;
+    return std::max(w, 1);
+}
+
 
 int validate(const vfp_params &p, std::string &why)
 {
@@ -230,7 +253,7 @@ int rebuild_units(vfp_batch *b)
     b->units.clear();
     for (int s : b->active) {
         const int n = b->hs[s].p.n;
-        const int w = choose_strip(n, b->cells);
+        const int w = b->staged == 3 ? choose_strip_c(n, b->cells, b->rotation) : choose_strip(n, b->cells);
         const int o0 = (b->K - 1) / 2;
         const int SY = b->staged == 2 ? (n >= 256 ? 256 : (n + 63) / 64 * 64) + 2 * kH : kSY;
         for (int i0 = 0; i0 < n; i0 += w)
@@ -259,9 +282,11 @@ int rebuild_units(vfp_batch *b)
         } else if (b->staged == 1) {
             bytes = (2 * (size_t)u.w * (n + 2 * kPad) + (size_t)(u.w + 2 * kH) * kSY +
                      (b->rotation ? (size_t)u.w * kSY : 0)) * 4;
-        } else {
+        } else if (b->staged == 2) {
             const size_t SY = (n >= 256 ? 256 : (n + 63) / 64 * 64) + 2 * kH;
             bytes = ((size_t)u.w * (n + 2 * kPad) + (size_t)(u.w + 2 * kH) * SY + (b->rotation ? (size_t)u.w * SY : 0)) * 4;
+        } else {
+            bytes = lds_bytes_c((int)n, u.w, b->rotation);
         }
         mx = std::max(mx, bytes);
     }
@@ -313,9 +338,11 @@ void launch_step_t(vfp_batch *b, int parity)
 template <int K, int WAKE, bool CL, int ROT>
 void launch_step32_t(vfp_batch *b, int parity)
 {
-    auto k = b->staged == 2 ? step32b_kernel<K, WAKE, CL, ROT> : step32_kernel<K, WAKE, CL, ROT>;
-    static int cur_a = 0, cur_b = 0;
-    lds_limit(k, b->lds_step, b->staged == 2 ? cur_b : cur_a);
+    auto k = b->staged == 3   ? step32c_kernel<K, WAKE, CL, ROT>
+             : b->staged == 2 ? step32b_kernel<K, WAKE, CL, ROT>
+                              : step32_kernel<K, WAKE, CL, ROT>;
+    static int cur[4] = {0, 0, 0, 0};
+    lds_limit(k, b->lds_step, cur[b->staged]);
     hipLaunchKernelGGL(k, dim3((unsigned)b->units.size()), dim3(kThreads), b->lds_step, b->stream,
                        b->d_sd, b->d_units, (int)b->units.size(), parity);
 }
@@ -390,7 +417,7 @@ int launch_tick(vfp_batch *b, int parity)
         auto wk = fp16 ? wake_mfma2_kernel<true> : wake_mfma2_kernel<false>;
         static int cur16 = 0, cur8 = 0;
         lds_limit(wk, b->lds_wake, fp16 ? cur16 : cur8);
-        hipLaunchKernelGGL(wk, dim3((unsigned)b->wtiles.size()), dim3(64), b->lds_wake, b->stream,
+        hipLaunchKernelGGL(wk, dim3((unsigned)b->wtiles.size()), dim3(kThreads), b->lds_wake, b->stream,
                            b->d_sd, b->d_wtiles, parity);
         if (b->timing) {
             int rc = timing_event(b, &t1);
@@ -750,6 +777,18 @@ int create_impl(const vfp_params *p, int32_t count, void *stream, void *ws, size
         d.pm = q.p_min / d.dp;
         d.tw = d.th * d.dp / d.dq;
         d.tk = d.th * d.dq / d.dp;
+        {
+            const double k1 = d.bt / 6.0, k2 = d.bt / (d.dp * d.dp);
+            d.fbx = (float)d.bx;
+            d.fby = (float)d.by;
+            d.fk1 = (float)k1;
+            d.fe[0] = (float)(2.0 * k1 + k2);
+            d.fe[1] = (float)(1.0 - 2.0 * k2);
+            d.fe[2] = (float)(6.0 * k1 + k2);
+            d.fe[3] = (float)(-2.0 * k1);
+            d.fd0 = (float)(-d.tw * d.pm);
+            d.fd1 = (float)(-d.tw);
+        }
         unsigned char *A = b->arena;
         d.psi[0] = A + h.off_psi[0];
         d.psi[1] = A + h.off_psi[1];
@@ -785,7 +824,8 @@ int create_impl(const vfp_params *p, int32_t count, void *stream, void *ws, size
                 hi = std::max(hi, std::max(a, c));
             }
         }
-        b->hs[s].fast = q.n % 4 == 0 && lo > -2.0 + 1e-9 && hi < 2.0 - 1e-9;
+        // (the margin covers FP32 evaluation of the displacement in the staged kernels)
+        b->hs[s].fast = q.n % 4 == 0 && lo > -2.0 + 1e-5 && hi < 2.0 - 1e-5;
     }
     b->lds_stats = 2 * (size_t)maxn * sizeof(double);
     HIPCHK(hipMemsetAsync(b->arena, 0, need, b->stream));
@@ -1095,13 +1135,22 @@ int vfp_batch_set_tuning(vfp_batch *b, int32_t cells_per_unit, int32_t use_graph
     if (cells * elem_size(b->precision) * 2 > 128 * 1024)
         return fail(VFP_EINVAL, "cells_per_unit too large for the workgroup's LDS");
     if (cells < 16) return fail(VFP_EINVAL, "cells_per_unit too small");
+    if (staged < 0 || staged > 3) return fail(VFP_EINVAL, "staged must be 0, 1, 2 or 3");
     HIPCHK(hipStreamSynchronize(b->stream));
     b->cells = cells;
     b->use_graph = use_graph != 0;
-    if (staged < 0 || staged > 2) return fail(VFP_EINVAL, "staged must be 0, 1 or 2");
     b->staged = staged;
     b->units_dirty = true;
     b->graph_valid = false;
+    return VFP_OK;
+}
+
+int vfp_batch_get_tuning(vfp_batch *b, int32_t *cells_per_unit, int32_t *use_graph, int32_t *staged)
+{
+    if (!b) return fail(VFP_EINVAL, "invalid arguments");
+    if (cells_per_unit) *cells_per_unit = b->cells;
+    if (use_graph) *use_graph = b->use_graph ? 1 : 0;
+    if (staged) *staged = b->staged;
     return VFP_OK;
 }
 
@@ -1263,7 +1312,7 @@ int vfp_batch_autotune(vfp_batch *b, int32_t ticks, int32_t *chosen_cells, int32
     const int staged0 = b->staged, cells0 = b->cells;
     b->every = 0;   // no records during trials
     b->timing = false;
-    std::vector<int> layouts = b->precision == VFP_FP64 ? std::vector<int>{0} : std::vector<int>{1, 2};
+    std::vector<int> layouts = b->precision == VFP_FP64 ? std::vector<int>{0} : std::vector<int>{1, 2, 3};
     std::vector<int> cand = {2048, 4096, 8192, 16384};
     hipEvent_t e0, e1;
     HIPCHK(hipEventCreate(&e0));

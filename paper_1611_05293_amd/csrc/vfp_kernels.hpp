@@ -51,6 +51,12 @@ struct SimDev {
     double *ring;                    // record rows (7 doubles each) or NULL
     int64_t ring_cap;
     int64_t *ring_rows;
+    // FP32 constants of the chunked staged kernel, rounded once on the host:
+    // bx, by (displacement per p row), k1 = beta*dtheta/6, the four
+    // p-independent damping/diffusion coefficients {2k1+k2, 1-2k2, 6k1+k2,
+    // -2k1} (k2 = beta*dtheta/dp^2), and the Manhattan drift shift
+    // -tw*(pm + row) as fd0 + row*fd1
+    float fbx, fby, fk1, fe[4], fd0, fd1, fpad;
 };
 
 struct Unit {
@@ -653,12 +659,14 @@ __device__ __forceinline__ void split16(float x, uint16_t &hi, uint16_t &lo)
 }
 
 // ---------------------------------------------------------------------
-// Matrix-core wake, one wave per (simulation, tile of 16 block columns).
-// The high and low 16-bit parts of the (power-of-two scaled) lag table are
-// made once at set-up (wake_split_kernel).  The wave stages rho's hi/lo
-// parts for the block columns it touches and two copies of its lag range,
-// reversed and offset by one element, so that every lane reads its four
-// consecutive Toeplitz entries as two aligned 32-bit words.
+// Matrix-core wake, one workgroup of kWaves waves per (simulation, tile of
+// 16 block columns).  The high and low 16-bit parts of the (power-of-two
+// scaled) lag table are made once at set-up (wake_split_kernel).  The
+// workgroup stages rho's hi/lo parts for the block columns the tile touches
+// and two copies of its lag range, reversed and offset by one element, so
+// that every lane reads its four consecutive Toeplitz entries as two aligned
+// 32-bit words.  The block diagonals d are dealt out to the waves in turn;
+// the per-wave partial products are added in FP64 in wave order.
 // ---------------------------------------------------------------------
 struct WakeTile {
     int32_t sim, tile, pad0, pad1;
@@ -677,13 +685,16 @@ __global__ void wake_split_kernel(int n, const double *__restrict__ wl64, double
 }
 
 template <bool FP16>
-__global__ __launch_bounds__(64) void wake_mfma2_kernel(const SimDev *__restrict__ sims,
-                                                        const WakeTile *__restrict__ tiles, int parity)
+__global__ __launch_bounds__(kThreads) void wake_mfma2_kernel(const SimDev *__restrict__ sims,
+                                                              const WakeTile *__restrict__ tiles, int parity)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
+    __shared__ double red[kThreads];
+    __shared__ double wsum[kWaves - 1][64][4];
     const WakeTile wt = tiles[blockIdx.x];
     const SimDev &sd = sims[wt.sim];
-    const int n = sd.n, lane = threadIdx.x, nb = (n + 15) / 16;
+    const int n = sd.n, tid = threadIdx.x, lane = tid & 63, nb = (n + 15) / 16;
+    const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int I0 = 16 * wt.tile;
     const int dmin = max(-(nb - 1), I0 - (nb - 1)), dmax = min(nb - 1, I0 + 15);
     const int Jlo = I0 - dmax;
@@ -697,19 +708,23 @@ __global__ __launch_bounds__(64) void wake_mfma2_kernel(const SimDev *__restrict
     const double *cs = sd.colsum[parity];
 
     double part = 0.0, mx = 0.0;
-    for (int k = lane; k < n; k += 64) {
+    for (int k = tid; k < n; k += kThreads) {
         part += cs[k];
         mx = fmax(mx, fabs(cs[k]));
     }
-    part = wave_sum(part);
+    part = block_sum(part, red);
     for (int off = 32; off > 0; off >>= 1) mx = fmax(mx, __shfl_xor(mx, off, 64));
+    if (lane == 0) red[wv] = mx;
+    __syncthreads();
+    mx = red[0];
+    for (int k = 1; k < kWaves; ++k) mx = fmax(mx, red[k]);
     const double Qh = part * sd.dq * sd.dp;
     const double s = sd.renorm ? sd.Q0 / Qh : 1.0;
     const double rmax = mx * s * sd.dp;
     int e = 0;
     if (FP16 && rmax > 0.0) { frexp(rmax, &e); e = 14 - e; }
     const double rscale = ldexp(s * sd.dp, e);
-    for (int k = lane; k < NR; k += 64) {
+    for (int k = tid; k < NR; k += kThreads) {
         const int g = 16 * Jlo + k;
         uint16_t h = 0, l = 0;
         if (g >= 0 && g < n) split16<FP16>((float)(cs[g] * rscale), h, l);
@@ -717,7 +732,7 @@ __global__ __launch_bounds__(64) void wake_mfma2_kernel(const SimDev *__restrict
         rlo[k] = l;
     }
     const uint16_t *wh = sd.wsplit, *wlo = sd.wsplit + (2 * n - 1);
-    for (int y = lane; y < NL + 1; y += 64) {
+    for (int y = tid; y < NL + 1; y += kThreads) {
         const int L0 = Lhi - y, L1 = Lhi - y - 1;
         const bool ok0 = L0 > -n && L0 < n && y < NL, ok1 = L1 > -n && L1 < n && y + 1 < NL;
         c0h[y] = ok0 ? wh[L0 + n - 1] : (uint16_t)0;
@@ -735,7 +750,7 @@ __global__ __launch_bounds__(64) void wake_mfma2_kernel(const SimDev *__restrict
     const uint16_t *ah = odd ? c1h + (y00 - 1) : c0h + y00;
     const uint16_t *al = odd ? c1l + (y00 - 1) : c0l + y00;
     v4f acc0 = {0.0f, 0.0f, 0.0f, 0.0f}, acc1 = acc0, acc2 = acc0;
-    for (int d = dmax; d >= dmin; --d) {
+    for (int d = dmax - wv; d >= dmin; d -= kWaves) {
         const int yo = 16 * (dmax - d);
         const uint2 A_h = make_uint2(*(const uint32_t *)(ah + yo), *(const uint32_t *)(ah + yo + 2));
         const uint2 A_l = make_uint2(*(const uint32_t *)(al + yo), *(const uint32_t *)(al + yo + 2));
@@ -752,12 +767,21 @@ __global__ __launch_bounds__(64) void wake_mfma2_kernel(const SimDev *__restrict
             acc2 = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(__builtin_bit_cast(v4s, A_l), __builtin_bit_cast(v4s, B_h), acc2, 0, 0, 0);
         }
     }
-    const double outscale = ldexp(sd.S, -e) * sd.sext[1];
-    for (int q = 0; q < 4; ++q) {
-        const int i = 16 * (I0 + a) + kq + q;
-        if (i < n) sd.vext[i] = (float)(((double)acc0[q] + ((double)acc1[q] + (double)acc2[q])) * outscale);
+    double t[4];
+    for (int q = 0; q < 4; ++q) t[q] = (double)acc0[q] + ((double)acc1[q] + (double)acc2[q]);
+    if (wv > 0)
+        for (int q = 0; q < 4; ++q) wsum[wv - 1][lane][q] = t[q];
+    __syncthreads();
+    if (wv == 0) {
+        const double outscale = ldexp(sd.S, -e) * sd.sext[1];
+        for (int q = 0; q < 4; ++q) {
+            double v = t[q];
+            for (int k = 0; k < kWaves - 1; ++k) v += wsum[k][lane][q];
+            const int i = 16 * (I0 + a) + kq + q;
+            if (i < n) sd.vext[i] = (float)(v * outscale);
+        }
+        if (wt.tile == 0 && lane == 0) sd.sext[0] = s;
     }
-    if (wt.tile == 0 && lane == 0) sd.sext[0] = s;
 }
 
 // CSR spectrum of the state whose profile the diagnostics kernel left in

@@ -1,0 +1,398 @@
+// vfp_step32c.hpp -- third layout of the FP32 staged step (included by
+// vfp.hip after vfp_step32b.hpp; chosen with the tuning switch).
+//
+// The same split step as step32_kernel (rotation, kick, damping/diffusion,
+// FP64 column sums), arranged so that every cell costs as few vector ALU
+// instructions as possible:
+//   * staging: each wave owns whole staged columns; a lane moves four rows
+//     with one 16-byte buffer load and one 16-byte LDS store.  The loads of
+//     the next chunk are issued before the rotation of the current one and
+//     consumed after it (register prefetch, kPF4 columns per wave).
+//   * rotation: the source displacement is evaluated in FP32 from per-column
+//     constants, dx = j*bx + (ax0 + i*axi); floor and fraction take one
+//     instruction each; the K*K taps are LDS reads at immediate offsets from
+//     one per-lane address.  The rotated values are stored unscaled.
+//   * kick + damping/diffusion: a wave owns a block of 256 rows (four per
+//     lane) and walks over the columns, so the four stencil coefficients of
+//     each row (with the renormalisation factor s and the zero rows outside
+//     the grid folded in) are formed once per block instead of per cell.
+// Chunks are CH = 192 rows for every grid size; a staged column holds
+// rows j0-4 .. j0+CH+3, so every 16-byte load is aligned (n % 4 == 0), and
+// its fixed length keeps all tap offsets compile-time immediates.
+// LDS: A[W][n + 2*kPad], S[W + 2*kH][CH + 8] and, for the Manhattan
+// rotation, Dm[W][CH + 8].
+#pragma once
+
+namespace vfp {
+
+constexpr int kCH = 192;          // rows per chunk
+constexpr int kSYC = kCH + 8;     // staged rows per column: j0-4 .. j0+kCH+3
+constexpr int kPF4 = 4;           // staged columns per wave held in registers across a chunk
+constexpr int kMaxStripC = 64;    // columns per work unit in this layout
+
+__device__ __forceinline__ int cvt_floor(float x)
+{
+    int m;
+    asm("v_cvt_flr_i32_f32 %0, %1" : "=v"(m) : "v"(x));
+    return m;
+}
+
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+
+// LDS byte address of a pointer into the workgroup's shared memory
+__device__ __forceinline__ unsigned lds_addr(const void *p)
+{
+    return (unsigned)(uintptr_t)(const __attribute__((address_space(3))) void *)p;
+}
+
+// The K x K stencil taps f[a][b] = S[addr/4 + a*kSYC + b] of one lane, read at
+// immediate offsets from a single address: columns a = 0, 1 as paired reads
+// (dword offsets up to 203), a = 2, 3 as single reads (byte offsets from
+// 1600).  The compiler would otherwise form one base register per column.
+// The reads complete (lgkmcnt 0) before the asm ends.
+static_assert(kSYC == 200, "tap offsets below are written for 200-row staged columns");
+template <int K>
+__device__ __forceinline__ void read_taps(unsigned addr, float (&f)[K][K])
+{
+    if constexpr (K == 4) {
+        f32x2 t0, t1, t2, t3;
+        float u0, u1, u2, u3, u4, u5, u6, u7;
+        asm volatile(
+            "ds_read2_b32 %0, %12 offset1:1\n\t"
+            "ds_read2_b32 %1, %12 offset0:2 offset1:3\n\t"
+            "ds_read2_b32 %2, %12 offset0:200 offset1:201\n\t"
+            "ds_read2_b32 %3, %12 offset0:202 offset1:203\n\t"
+            "ds_read_b32 %4, %12 offset:1600\n\t"
+            "ds_read_b32 %5, %12 offset:1604\n\t"
+            "ds_read_b32 %6, %12 offset:1608\n\t"
+            "ds_read_b32 %7, %12 offset:1612\n\t"
+            "ds_read_b32 %8, %12 offset:2400\n\t"
+            "ds_read_b32 %9, %12 offset:2404\n\t"
+            "ds_read_b32 %10, %12 offset:2408\n\t"
+            "ds_read_b32 %11, %12 offset:2412\n\t"
+            "s_waitcnt lgkmcnt(0)"
+            : "=&v"(t0), "=&v"(t1), "=&v"(t2), "=&v"(t3), "=&v"(u0), "=&v"(u1), "=&v"(u2), "=&v"(u3),
+              "=&v"(u4), "=&v"(u5), "=&v"(u6), "=&v"(u7)
+            : "v"(addr));
+        f[0][0] = t0.x; f[0][1] = t0.y; f[0][2] = t1.x; f[0][3] = t1.y;
+        f[1][0] = t2.x; f[1][1] = t2.y; f[1][2] = t3.x; f[1][3] = t3.y;
+        f[2][0] = u0; f[2][1] = u1; f[2][2] = u2; f[2][3] = u3;
+        f[3][0] = u4; f[3][1] = u5; f[3][2] = u6; f[3][3] = u7;
+    } else {
+        f32x2 t0, t1;
+        float u0, u1, u2, u3, u4;
+        asm volatile(
+            "ds_read2_b32 %0, %7 offset1:1\n\t"
+            "ds_read_b32 %2, %7 offset:8\n\t"
+            "ds_read2_b32 %1, %7 offset0:200 offset1:201\n\t"
+            "ds_read_b32 %3, %7 offset:808\n\t"
+            "ds_read_b32 %4, %7 offset:1600\n\t"
+            "ds_read_b32 %5, %7 offset:1604\n\t"
+            "ds_read_b32 %6, %7 offset:1608\n\t"
+            "s_waitcnt lgkmcnt(0)"
+            : "=&v"(t0), "=&v"(t1), "=&v"(u0), "=&v"(u1), "=&v"(u2), "=&v"(u3), "=&v"(u4)
+            : "v"(addr));
+        f[0][0] = t0.x; f[0][1] = t0.y; f[0][2] = u0;
+        f[1][0] = t1.x; f[1][1] = t1.y; f[1][2] = u1;
+        f[2][0] = u2; f[2][1] = u3; f[2][2] = u4;
+    }
+}
+
+template <int K, int WAKE, bool CLAMP, int ROT>
+__global__ __launch_bounds__(kThreads) void step32c_kernel(const SimDev *__restrict__ sims,
+                                                           const Unit *__restrict__ units, int nunits,
+                                                           int parity)
+{
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    __shared__ double red[kThreads];
+    __shared__ __align__(16) float sh_kw[kMaxStripC][4];
+    __shared__ int sh_km[kMaxStripC];
+    __shared__ float sh_rw[kMaxStripC][4];
+    __shared__ int sh_rm[kMaxStripC];
+    constexpr int o0 = (K - 1) / 2;
+
+    const Unit u = units[xcd_unit(blockIdx.x, nunits)];
+    const SimDev &sd = sims[u.sim];
+    const int n = sd.n, W = u.w, i0 = u.i0, tid = threadIdx.x, lane = tid & 63;
+    const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int LA = n + 2 * kPad;
+    constexpr int CH = kCH, SY = kSYC, Q4 = SY / 4;
+    const int SX = W + 2 * kH;
+    float *A = (float *)smem_raw;
+    float *S = A + (size_t)W * LA;
+    float *Dm = S + (size_t)SX * SY;
+    const float *__restrict__ src = (const float *)sd.psi[parity];
+    float *__restrict__ dst = (float *)sd.psi[parity ^ 1];
+    const double *__restrict__ cs = sd.colsum[parity];
+    double *__restrict__ cs_next = sd.colsum[parity ^ 1];
+
+    // ---- prologue: renormalisation factor, wake slice, kick weights, pads
+    double s;
+    if constexpr (WAKE == WAKE_EXTERNAL) {
+        s = sd.sext[0];
+    } else {
+        double part = 0.0;
+        for (int k = tid; k < n; k += kThreads) part += cs[k];
+        const double Qh = block_sum(part, red) * sd.dq * sd.dp;
+        s = sd.renorm ? sd.Q0 / Qh : 1.0;
+    }
+    double shift = 0.0;                       // kick of column tid (tid < W), in rows
+    if constexpr (WAKE == WAKE_FUSED) {
+        const int parts = kThreads / W;
+        const int c = tid / parts, pt = tid - c * parts;
+        double acc = 0.0;
+        if (c < W) {
+            const int i = i0 + c;
+            float a32 = 0.0f;
+            int cnt = 0;
+            for (int j = pt; j < n; j += parts) {
+                a32 = fmaf(sd.wl32[i - j + n - 1], (float)(sd.dp * cs[j]), a32);
+                if (++cnt == 32) { acc += a32; a32 = 0.0f; cnt = 0; }
+            }
+            acc += a32;
+        }
+        __syncthreads();
+        red[tid] = acc;
+        __syncthreads();
+        if (tid < W) {
+            double v = 0.0;
+            for (int k = 0; k < parts; ++k) v += red[tid * parts + k];
+            shift = sd.S * s * v * sd.kick;
+            sd.vext[i0 + tid] = (float)(sd.S * s * v);      // the wake this step used
+        }
+    } else if constexpr (WAKE == WAKE_EXTERNAL) {
+        if (tid < W) shift = (double)sd.vext[i0 + tid] * sd.kick;
+    }
+    if (tid < W) {
+        const double fl = floor(shift);
+        float l[K];
+        lagrange_fma<K>((float)(shift - fl), l);
+        for (int k = 0; k < K; ++k) sh_kw[tid][k] = l[k];
+        for (int k = K; k < 4; ++k) sh_kw[tid][k] = 0.0f;
+        sh_km[tid] = (int)fmax(fmin(fl, 1.0e6), -1.0e6);
+    }
+    if constexpr (ROT == 1) {
+        // RF kick of column i pulls along p from p + dtheta*q_i: shift tk*(q_min/dq + i) rows
+        if (tid < W) {
+            const double sh = sd.tk * (sd.q_min / sd.dq + (double)(i0 + tid));
+            const double fl = floor(sh);
+            float l[K];
+            lagrange_fma<K>((float)(sh - fl), l);
+            for (int k = 0; k < K; ++k) sh_rw[tid][k] = l[k];
+            for (int k = K; k < 4; ++k) sh_rw[tid][k] = 0.0f;
+            sh_rm[tid] = (int)fl;
+        }
+    }
+    for (int k = tid; k < W * 2 * kPad; k += kThreads) {
+        const int c = k / (2 * kPad), r = k - c * (2 * kPad);
+        A[c * LA + (r < kPad ? r : n + r)] = 0.0f;
+    }
+
+    // ---- phase R: chunks of CH rows
+    // staged column x is source column i0 - kH + x; its LDS row y is row j0 - 4 + y;
+    // lane l moves rows j0 - 4 + 4l .. +3 (lanes l < Q4)
+    const int ncolw = (SX - wv + kWaves - 1) / kWaves;
+    const bool lane_ld = lane < Q4;
+    u32x4 pf[kPF4];
+    auto load_cols = [&](int j0, int cw0) {
+        // rows above the grid (first chunk, lane 0) get an offset far past the
+        // column instead of a negative one, so the 16-byte range check cannot wrap
+        const int row = j0 - 4 + 4 * lane;
+        const int voff = row >= 0 ? row * 4 : 0x40000000;
+#pragma unroll
+        for (int k = 0; k < kPF4; ++k) {
+            const int x = wv + kWaves * (cw0 + k), gi = i0 - kH + x;
+            if (cw0 + k < ncolw && lane_ld) {
+                const bool ok = gi >= 0 && gi < n;
+                const __amdgpu_buffer_rsrc_t r = column_rsrc(src + (size_t)(ok ? gi : 0) * n, ok ? n : 0);
+                pf[k] = __builtin_amdgcn_raw_buffer_load_b128(r, voff, 0, 0);
+            }
+        }
+    };
+    auto store_cols = [&](int cw0) {
+#pragma unroll
+        for (int k = 0; k < kPF4; ++k) {
+            const int x = wv + kWaves * (cw0 + k);
+            if (cw0 + k < ncolw && lane_ld) *(u32x4 *)(S + x * SY + 4 * lane) = pf[k];
+        }
+    };
+    load_cols(0, 0);
+    for (int j0 = 0; j0 < n; j0 += CH) {
+        __syncthreads();
+        store_cols(0);
+        for (int cw0 = kPF4; cw0 < ncolw; cw0 += kPF4) {       // columns beyond the prefetch
+            load_cols(j0, cw0);
+            store_cols(cw0);
+        }
+        __syncthreads();
+        if (j0 + CH < n) load_cols(j0 + CH, 0);
+        if constexpr (ROT == 0) {
+            const float bxf = sd.fbx, byf = sd.fby;
+            for (int c = wv; c < W; c += kWaves) {
+                const double ic = (double)(i0 + c);
+                const float Xc = (float)fma(ic, sd.axi, sd.ax0);
+                const float Yc = (float)fma(ic, sd.cyi, sd.cy0);
+                // LDS byte address of the stencil corner for zero displacement
+                const int cb4 = (int)lds_addr(S + (c + kH - o0) * SY + lane + 4 - o0);
+                float *acol = A + c * LA + kPad + j0 + lane;
+#pragma unroll
+                for (int rb = 0; rb < kCH; rb += 64) {
+                    if (j0 + rb >= n) break;
+                    const int j = j0 + rb + lane;
+                    if (j < n) {
+                        const float jf = (float)j;
+                        const float dx = fmaf(jf, bxf, Xc), dy = fmaf(jf, byf, Yc);
+                        const int mx = cvt_floor(dx), my = cvt_floor(dy);
+                        float lx[K], ly[K];
+                        lagrange_fma<K>(__builtin_amdgcn_fractf(dx), lx);
+                        lagrange_fma<K>(__builtin_amdgcn_fractf(dy), ly);
+                        float f[K][K];
+                        read_taps<K>((unsigned)(__mul24(mx, 4 * SY) + cb4 + 4 * rb + 4 * my), f);
+                        float v;
+#pragma unroll
+                        for (int a = 0; a < K; ++a) {
+                            float r = ly[0] * f[a][0];
+#pragma unroll
+                            for (int b = 1; b < K; ++b) r = fmaf(ly[b], f[a][b], r);
+                            v = a == 0 ? lx[0] * r : fmaf(lx[a], r, v);
+                        }
+                        if constexpr (CLAMP) {
+                            const float lo = fminf(fminf(f[o0][o0], f[o0][o0 + 1]), fminf(f[o0 + 1][o0], f[o0 + 1][o0 + 1]));
+                            const float hi = fmaxf(fmaxf(f[o0][o0], f[o0][o0 + 1]), fmaxf(f[o0 + 1][o0], f[o0 + 1][o0 + 1]));
+                            v = fminf(fmaxf(v, lo), hi);
+                        }
+                        acol[rb] = v;
+                    }
+                }
+            }
+        } else {
+            // drift along q, one shift per staged row (row j0 - 4 + y), rows split over the waves
+            for (int y = tid; y < SY; y += kThreads) {
+                const float sh = fmaf((float)(j0 - 4 + y), sd.fd1, sd.fd0);
+                const int fl = cvt_floor(sh);
+                float l[K];
+                lagrange_fma<K>(__builtin_amdgcn_fractf(sh), l);
+                const float *col = S + (kH + fl - o0) * SY + y;
+                for (int c = 0; c < W; ++c, col += SY) {
+                    float f[K];
+#pragma unroll
+                    for (int k = 0; k < K; ++k) f[k] = col[k * SY];
+                    float v = l[0] * f[0];
+#pragma unroll
+                    for (int k = 1; k < K; ++k) v = fmaf(l[k], f[k], v);
+                    if constexpr (CLAMP) v = fminf(fmaxf(v, fminf(f[o0], f[o0 + 1])), fmaxf(f[o0], f[o0 + 1]));
+                    Dm[c * SY + y] = v;
+                }
+            }
+            __syncthreads();
+            // RF kick along p, one shift per column
+            for (int c = wv; c < W; c += kWaves) {
+                float rw[K];
+#pragma unroll
+                for (int k = 0; k < K; ++k) rw[k] = sh_rw[c][k];
+                const float *col = Dm + c * SY + lane + 4 + sh_rm[c] - o0;
+                float *acol = A + c * LA + kPad + j0 + lane;
+#pragma unroll
+                for (int rb = 0; rb < kCH; rb += 64) {
+                    if (j0 + rb >= n) break;
+                    if (j0 + rb + lane < n) {
+                        float f[K];
+#pragma unroll
+                        for (int k = 0; k < K; ++k) f[k] = col[rb + k];
+                        float v = rw[0] * f[0];
+#pragma unroll
+                        for (int k = 1; k < K; ++k) v = fmaf(rw[k], f[k], v);
+                        if constexpr (CLAMP) v = fminf(fmaxf(v, fminf(f[o0], f[o0 + 1])), fmaxf(f[o0], f[o0 + 1]));
+                        acol[rb] = v;
+                    }
+                }
+            }
+        }
+    }
+    __syncthreads();
+
+    // ---- kick and damping/diffusion.  Output row j uses the kicked values of
+    // rows j-1 .. j+2 with coefficients s*(e_k + ku_j*d_k), ku_j = k1*p_j/dp,
+    // d = (-2, -3, 6, -1); a lane's four rows need the kicked rows j-1 .. j+5,
+    // which read A rows j-1+km-o0 .. j+5+km-o0+K-1.
+    const int nb = (n + 255) >> 8;                 // 256-row blocks
+    int b0 = nb, bst = kWaves, c0 = 0, cst = 1;
+    if (nb >= kWaves) {
+        b0 = wv;
+    } else {
+        const int g = kWaves / nb;
+        if (wv < nb * g) { b0 = wv % nb; bst = nb; c0 = wv / nb; cst = g; }
+    }
+    const float sf = (float)s;
+    const float sk1 = sf * sd.fk1;
+    const float se0 = sf * sd.fe[0], se1 = sf * sd.fe[1], se2 = sf * sd.fe[2], se3 = sf * sd.fe[3];
+    for (int b = b0; b < nb; b += bst) {
+        const int j = 256 * b + 4 * lane;
+        const bool act = j < n;
+        float C[4][4];
+        {
+            const float ku0 = sk1 * (float)(sd.pm + (double)j);
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const float ku = fmaf(sk1, (float)r, ku0);
+                C[r][0] = fmaf(-2.0f, ku, se0);
+                C[r][1] = fmaf(-3.0f, ku, se1);
+                C[r][2] = fmaf(6.0f, ku, se2);
+                C[r][3] = se3 - ku;
+            }
+            if (j == 0) C[0][0] = 0.0f;                          // row -1 is outside the grid
+            if (j + 4 == n) { C[2][3] = 0.0f; C[3][2] = 0.0f; C[3][3] = 0.0f; }   // rows n, n+1
+        }
+        for (int c = c0; c < W; c += cst) {
+            double part = 0.0;
+            if (act) {
+                const int km = sh_km[c];
+                const float4 w4 = *(const float4 *)sh_kw[c];
+                const float w[4] = {w4.x, w4.y, w4.z, w4.w};
+                const float *acol = A + c * LA + kPad;
+                const int st = km - o0 - 1;                     // first A row read, relative to j
+                const bool fast = st >= -kPad && km - o0 + K <= kPad - 1;
+                float f[K + 6];
+                if (fast) {
+#pragma unroll
+                    for (int k = 0; k < K + 6; ++k) f[k] = acol[j + st + k];
+                } else {
+#pragma unroll
+                    for (int k = 0; k < K + 6; ++k) {
+                        const int jj = j + st + k;
+                        f[k] = (jj >= 0 && jj < n) ? acol[jj] : 0.0f;
+                    }
+                }
+                float g[7];                                     // kicked rows j-1 .. j+5
+#pragma unroll
+                for (int r = 0; r < 7; ++r) {
+                    float v = w[0] * f[r];
+#pragma unroll
+                    for (int k = 1; k < K; ++k) v = fmaf(w[k], f[r + k], v);
+                    if constexpr (CLAMP) {
+                        const float p0 = f[r + o0], p1 = f[r + o0 + 1];
+                        v = fminf(fmaxf(v, fminf(p0, p1)), fmaxf(p0, p1));
+                    }
+                    g[r] = v;
+                }
+                float o[4];
+#pragma unroll
+                for (int r = 0; r < 4; ++r)
+                    o[r] = fmaf(C[r][3], g[r + 3], fmaf(C[r][2], g[r + 2], fmaf(C[r][1], g[r + 1], C[r][0] * g[r])));
+                *(float4 *)(dst + (size_t)(i0 + c) * n + j) = make_float4(o[0], o[1], o[2], o[3]);
+                part = (double)((o[0] + o[1]) + (o[2] + o[3]));
+            }
+            part = wave_sum(part);
+            if (lane == 0) red[c * nb + b] = part;
+        }
+    }
+    __syncthreads();
+    if (tid < W) {
+        double t = 0.0;
+        for (int b = 0; b < nb; ++b) t += red[tid * nb + b];
+        cs_next[i0 + tid] = t;
+    }
+}
+
+}  // namespace vfp

@@ -94,6 +94,7 @@ def load():
             "vfp_batch_steps_done": (C.c_int, [h, C.c_int32, C.POINTER(C.c_int64)]),
             "vfp_batch_destroy": (None, [h]),
             "vfp_batch_set_tuning": (C.c_int, [h, C.c_int32, C.c_int32, C.c_int32]),
+            "vfp_batch_get_tuning": (C.c_int, [h, C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.POINTER(C.c_int32)]),
             "vfp_batch_autotune": (C.c_int, [h, C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]),
             "vfp_device_arch": (C.c_int, [C.c_char_p, C.c_int32]),
             "vfp_batch_kernel_timing": (C.c_int, [h, C.c_int32]),
@@ -248,6 +249,12 @@ class Batch:
 
     def set_tuning(self, cells_per_unit: int = 0, use_graph: bool = True, staged: int = 1):
         _check(load().vfp_batch_set_tuning(self._h, int(cells_per_unit), int(bool(use_graph)), int(staged)))
+
+    def get_tuning(self) -> tuple:
+        """(cells per unit, graph replay, kernel layout) in force."""
+        c, g, l = C.c_int32(), C.c_int32(), C.c_int32()
+        _check(load().vfp_batch_get_tuning(self._h, C.byref(c), C.byref(g), C.byref(l)))
+        return c.value, bool(g.value), l.value
 
     def autotune(self, ticks: int = 20, cache: Optional[str] = None) -> tuple:
         """Pick cells per unit and kernel layout by timing (vfp_batch_autotune).

@@ -70,7 +70,7 @@ def test_autotune_preserves_state_and_results():
     b = vfp.Batch([vfp.sim_kwargs(s, precision="fp32") for s in sims])
     b.step(5)
     cells, layout = b.autotune(ticks=4)
-    assert cells in (2048, 4096, 8192, 16384) and layout in (1, 2)
+    assert cells in (2048, 4096, 8192, 16384) and layout in (1, 2, 3)
     assert all(b.steps_done(i) == 5 for i in range(len(sims)))
     b.step(15)
     for i, s in enumerate(sims):
@@ -162,12 +162,13 @@ def test_haissinski_start_matches_oracle():
     assert np.abs(b.profile(0) - h0).max() < 0.1 * np.abs(b.profile(1) - g0).max()
 
 
-@pytest.mark.parametrize("staged", [0, 1, 2])
+@pytest.mark.parametrize("staged", [0, 1, 2, 3])
 @pytest.mark.parametrize("rotation", [0, 1])
 @pytest.mark.parametrize("clamp", [0, 1])
 def test_kernel_variants_match_oracle(staged, rotation, clamp):
     """Every FP32 kernel layout (generic, staged 64-row chunks, staged 256-row
-    chunks with the merged kick) and both rotations against the oracle."""
+    chunks with the merged kick, staged 192-row chunks with 16-byte staging and
+    per-row damping coefficients) and both rotations against the oracle."""
     sims = mixed_sims()
     for s in sims:
         s.rotation, s.clamp = rotation, clamp
