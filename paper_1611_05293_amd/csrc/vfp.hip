@@ -211,7 +211,7 @@ struct vfp_batch {
     size_t stage_elems = 0;
     size_t lds_step = 0, lds_stats = 0, lds_wake = 0;
     bool fast = false;             // all active simulations use the FP32 staged kernel
-    int staged = 1;                // tuning: 0 generic kernel, 1 / 2 the staged FP32 layouts
+    int staged = 3;                // tuning: 0 generic kernel, 1, 2, 3 the staged FP32 layouts
     std::vector<WakeTile> wtiles;
     WakeTile *d_wtiles = nullptr;
     size_t wtiles_cap = 0;

@@ -705,12 +705,27 @@ __global__ __launch_bounds__(kThreads) void wake_mfma2_kernel(const SimDev *__re
     uint16_t *rhi = (uint16_t *)smem_raw;
     uint16_t *rlo = rhi + NR;
     uint16_t *c0h = rlo + NR, *c0l = c0h + NLp, *c1h = c0l + NLp, *c1l = c1h + NLp;
-    const double *cs = sd.colsum[parity];
+    typedef const __attribute__((address_space(1))) double gdouble;
+    typedef const __attribute__((address_space(1))) uint16_t gu16;
+    gdouble *cs = (gdouble *)sd.colsum[parity];
 
+    // lag range, copy 0 (branch-free loads, so the unrolled loop issues them together)
+    gu16 *wh = (gu16 *)sd.wsplit, *wlo = (gu16 *)(sd.wsplit + (2 * n - 1));
+#pragma unroll 8
+    for (int y = tid; y < NL + 1; y += kThreads) {
+        const int L0 = Lhi - y;
+        const bool ok0 = L0 > -n && L0 < n && y < NL;
+        const int ix = ok0 ? L0 + n - 1 : 0;
+        const uint16_t h = wh[ix], l = wlo[ix];
+        c0h[y] = ok0 ? h : (uint16_t)0;
+        c0l[y] = ok0 ? l : (uint16_t)0;
+    }
     double part = 0.0, mx = 0.0;
+#pragma unroll 8
     for (int k = tid; k < n; k += kThreads) {
-        part += cs[k];
-        mx = fmax(mx, fabs(cs[k]));
+        const double v = cs[k];
+        part += v;
+        mx = fmax(mx, fabs(v));
     }
     part = block_sum(part, red);
     for (int off = 32; off > 0; off >>= 1) mx = fmax(mx, __shfl_xor(mx, off, 64));
@@ -724,21 +739,22 @@ __global__ __launch_bounds__(kThreads) void wake_mfma2_kernel(const SimDev *__re
     int e = 0;
     if (FP16 && rmax > 0.0) { frexp(rmax, &e); e = 14 - e; }
     const double rscale = ldexp(s * sd.dp, e);
+#pragma unroll 8
     for (int k = tid; k < NR; k += kThreads) {
         const int g = 16 * Jlo + k;
-        uint16_t h = 0, l = 0;
-        if (g >= 0 && g < n) split16<FP16>((float)(cs[g] * rscale), h, l);
+        const bool ok = g >= 0 && g < n;
+        const double v = cs[ok ? g : 0];
+        uint16_t h, l;
+        split16<FP16>((float)((ok ? v : 0.0) * rscale), h, l);
         rhi[k] = h;
         rlo[k] = l;
     }
-    const uint16_t *wh = sd.wsplit, *wlo = sd.wsplit + (2 * n - 1);
+    __syncthreads();
+    // copy 1 is copy 0 shifted by one lag
     for (int y = tid; y < NL + 1; y += kThreads) {
-        const int L0 = Lhi - y, L1 = Lhi - y - 1;
-        const bool ok0 = L0 > -n && L0 < n && y < NL, ok1 = L1 > -n && L1 < n && y + 1 < NL;
-        c0h[y] = ok0 ? wh[L0 + n - 1] : (uint16_t)0;
-        c0l[y] = ok0 ? wlo[L0 + n - 1] : (uint16_t)0;
-        c1h[y] = ok1 ? wh[L1 + n - 1] : (uint16_t)0;
-        c1l[y] = ok1 ? wlo[L1 + n - 1] : (uint16_t)0;
+        const bool ok = y + 1 <= NL;
+        c1h[y] = ok ? c0h[y + 1] : (uint16_t)0;
+        c1l[y] = ok ? c0l[y + 1] : (uint16_t)0;
     }
     __syncthreads();
 

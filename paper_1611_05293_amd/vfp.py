@@ -247,7 +247,7 @@ class Batch:
         _check(load().vfp_batch_steps_done(self._h, i, C.byref(v)))
         return v.value
 
-    def set_tuning(self, cells_per_unit: int = 0, use_graph: bool = True, staged: int = 1):
+    def set_tuning(self, cells_per_unit: int = 0, use_graph: bool = True, staged: int = 3):
         _check(load().vfp_batch_set_tuning(self._h, int(cells_per_unit), int(bool(use_graph)), int(staged)))
 
     def get_tuning(self) -> tuple:
