@@ -77,9 +77,9 @@ int choose_strip(int n, int cells)
 }
 
 // Strip width of the chunked staged layout: at most kMaxStripC columns, the
-// per-(column, 256-row block) partial sums fit the workgroup's reduction
-// array, and a grid with more than one chunk keeps every staged column of a
-// wave in the prefetch registers.
+// per-(column, 256-row block, lane) partial sums fit the staging buffer
+// (W * nb * 64 <= (W + 2*kH) * kSYC floats), and a grid with more than one
+// chunk keeps every staged column of a wave in the prefetch registers.
 // The dynamic LDS of a unit stays under kLdsBudgetC so that five workgroups
 // fit on a compute unit.
 constexpr size_t kLdsBudgetC = 28 * 1024;
@@ -91,7 +91,7 @@ int choose_strip_c(int n, int cells, int rotation)
 {
     int w = std::max(1, std::min(cells / n, std::min(n, kMaxStripC)));
     const int nb = (n + 255) / 256;
-    w = std::min(w, kThreads / nb);
+    while (w > 1 && (size_t)w * nb * 64 > (size_t)(w + 2 * kH) * kSYC) --w;
     if (n > kCH) w = std::min(w, kWaves * kPF4 - 2 * kH);
     while (w > 1 && lds_bytes_c(n, w, rotation) > kLdsBudgetC) --w;
     return std::max(w, 1);

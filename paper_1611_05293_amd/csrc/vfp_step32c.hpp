@@ -99,6 +99,38 @@ __device__ __forceinline__ void read_taps(unsigned addr, float (&f)[K][K])
     }
 }
 
+// Kick and damping/diffusion of four consecutive rows j .. j+3 of one column.
+// a points at A row j + st - SH (16-byte aligned), where st = km - o0 - 1 is
+// the first row the kick reads and SH = st mod 4, so the K+6 values needed
+// are read as aligned 16-byte words (conflict-free for lanes four rows apart).
+template <int K, bool CLAMP, int SH>
+__device__ __forceinline__ void kick_damp4(const float *a, const float (&w)[4], const float (&C)[4][4], float (&o)[4])
+{
+    constexpr int o0 = (K - 1) / 2;
+    constexpr int NQ = (SH + K + 6 + 3) / 4;
+    float buf[4 * NQ];
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+        const float4 v = *(const float4 *)(a + 4 * q);
+        buf[4 * q] = v.x; buf[4 * q + 1] = v.y; buf[4 * q + 2] = v.z; buf[4 * q + 3] = v.w;
+    }
+    float g[7];                                     // kicked rows j-1 .. j+5
+#pragma unroll
+    for (int r = 0; r < 7; ++r) {
+        float v = w[0] * buf[SH + r];
+#pragma unroll
+        for (int k = 1; k < K; ++k) v = fmaf(w[k], buf[SH + r + k], v);
+        if constexpr (CLAMP) {
+            const float p0 = buf[SH + r + o0], p1 = buf[SH + r + o0 + 1];
+            v = fminf(fmaxf(v, fminf(p0, p1)), fmaxf(p0, p1));
+        }
+        g[r] = v;
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+        o[r] = fmaf(C[r][3], g[r + 3], fmaf(C[r][2], g[r + 2], fmaf(C[r][1], g[r + 1], C[r][0] * g[r])));
+}
+
 template <int K, int WAKE, bool CLAMP, int ROT>
 __global__ __launch_bounds__(kThreads) void step32c_kernel(const SimDev *__restrict__ sims,
                                                            const Unit *__restrict__ units, int nunits,
@@ -327,6 +359,7 @@ __global__ __launch_bounds__(kThreads) void step32c_kernel(const SimDev *__restr
     const float sf = (float)s;
     const float sk1 = sf * sd.fk1;
     const float se0 = sf * sd.fe[0], se1 = sf * sd.fe[1], se2 = sf * sd.fe[2], se3 = sf * sd.fe[3];
+    float *Sp = S;     // per-lane partial sums of the outputs, [W][nb][64] (fits: host bound)
     for (int b = b0; b < nb; b += bst) {
         const int j = 256 * b + 4 * lane;
         const bool act = j < n;
@@ -345,53 +378,64 @@ __global__ __launch_bounds__(kThreads) void step32c_kernel(const SimDev *__restr
             if (j + 4 == n) { C[2][3] = 0.0f; C[3][2] = 0.0f; C[3][3] = 0.0f; }   // rows n, n+1
         }
         for (int c = c0; c < W; c += cst) {
-            double part = 0.0;
+            float part = 0.0f;
             if (act) {
                 const int km = sh_km[c];
                 const float4 w4 = *(const float4 *)sh_kw[c];
                 const float w[4] = {w4.x, w4.y, w4.z, w4.w};
                 const float *acol = A + c * LA + kPad;
                 const int st = km - o0 - 1;                     // first A row read, relative to j
-                const bool fast = st >= -kPad && km - o0 + K <= kPad - 1;
-                float f[K + 6];
-                if (fast) {
-#pragma unroll
-                    for (int k = 0; k < K + 6; ++k) f[k] = acol[j + st + k];
-                } else {
+                const int sh = st & 3, q0 = st - sh;            // aligned start (q0 % 4 == 0)
+                const int nq = (sh + K + 6 + 3) / 4;
+                float o[4];
+                if (q0 >= -kPad && q0 + 4 * nq <= kPad + 4) {
+                    const float *a = acol + j + q0;
+                    switch (sh) {
+                    case 0: kick_damp4<K, CLAMP, 0>(a, w, C, o); break;
+                    case 1: kick_damp4<K, CLAMP, 1>(a, w, C, o); break;
+                    case 2: kick_damp4<K, CLAMP, 2>(a, w, C, o); break;
+                    default: kick_damp4<K, CLAMP, 3>(a, w, C, o); break;
+                    }
+                } else {                                        // kick beyond the zero pads
+                    float f[K + 6];
 #pragma unroll
                     for (int k = 0; k < K + 6; ++k) {
                         const int jj = j + st + k;
                         f[k] = (jj >= 0 && jj < n) ? acol[jj] : 0.0f;
                     }
-                }
-                float g[7];                                     // kicked rows j-1 .. j+5
+                    float g[7];
 #pragma unroll
-                for (int r = 0; r < 7; ++r) {
-                    float v = w[0] * f[r];
+                    for (int r = 0; r < 7; ++r) {
+                        float v = w[0] * f[r];
 #pragma unroll
-                    for (int k = 1; k < K; ++k) v = fmaf(w[k], f[r + k], v);
-                    if constexpr (CLAMP) {
-                        const float p0 = f[r + o0], p1 = f[r + o0 + 1];
-                        v = fminf(fmaxf(v, fminf(p0, p1)), fmaxf(p0, p1));
+                        for (int k = 1; k < K; ++k) v = fmaf(w[k], f[r + k], v);
+                        if constexpr (CLAMP) {
+                            const float p0 = f[r + o0], p1 = f[r + o0 + 1];
+                            v = fminf(fmaxf(v, fminf(p0, p1)), fmaxf(p0, p1));
+                        }
+                        g[r] = v;
                     }
-                    g[r] = v;
-                }
-                float o[4];
 #pragma unroll
-                for (int r = 0; r < 4; ++r)
-                    o[r] = fmaf(C[r][3], g[r + 3], fmaf(C[r][2], g[r + 2], fmaf(C[r][1], g[r + 1], C[r][0] * g[r])));
+                    for (int r = 0; r < 4; ++r)
+                        o[r] = fmaf(C[r][3], g[r + 3], fmaf(C[r][2], g[r + 2], fmaf(C[r][1], g[r + 1], C[r][0] * g[r])));
+                }
                 *(float4 *)(dst + (size_t)(i0 + c) * n + j) = make_float4(o[0], o[1], o[2], o[3]);
-                part = (double)((o[0] + o[1]) + (o[2] + o[3]));
+                part = (o[0] + o[1]) + (o[2] + o[3]);
             }
-            part = wave_sum(part);
-            if (lane == 0) red[c * nb + b] = part;
+            Sp[(c * nb + b) * 64 + lane] = part;              // the staging buffer is free now
         }
     }
     __syncthreads();
-    if (tid < W) {
+    // FP64 column sums: g threads per column, each adding every g-th partial
+    // of its column, then a reduction over the g lanes (fixed order)
+    {
+        const int g = W <= 4 ? 64 : W <= 8 ? 32 : W <= 16 ? 16 : W <= 32 ? 8 : 4;
+        const int c = tid / g, sub = tid - c * g;
         double t = 0.0;
-        for (int b = 0; b < nb; ++b) t += red[tid * nb + b];
-        cs_next[i0 + tid] = t;
+        if (c < W)
+            for (int k = sub; k < nb * 64; k += g) t += (double)Sp[c * nb * 64 + k];
+        for (int off = g >> 1; off > 0; off >>= 1) t += __shfl_xor(t, off, 64);
+        if (c < W && sub == 0) cs_next[i0 + c] = t;
     }
 }
 

@@ -190,3 +190,22 @@ def test_autotune_cache_roundtrip(tmp_path):
     assert b.autotune(ticks=2, cache=cache) == first          # served from the cache
     import json
     assert len(json.load(open(cache))) == 1
+
+
+@pytest.mark.parametrize("staged", [0, 1, 2, 3])
+def test_strong_kick_every_read_path(staged):
+    """Wakes strong enough that the kick moves columns by up to 6 rows (every
+    alignment of the aligned kick reads) and by more than the zero pads (the
+    bounds-checked path), in every FP32 layout, against the oracle."""
+    sims = [small_sim(n=64, steps=160, S=600.0, Pi=0.5, seed=3, lo=-7.0, hi=7.0),
+            small_sim(n=64, steps=160, S=1500.0, Pi=0.5, seed=4, lo=-7.0, hi=7.0),
+            small_sim(n=128, steps=320, S=600.0, Pi=0.7, seed=5, lo=-8.0, hi=8.0)]
+    b = vfp.Batch([vfp.sim_kwargs(s, precision="fp32") for s in sims])
+    b.set_tuning(0, True, staged)
+    nt = 3
+    b.step(nt)
+    for i, s in enumerate(sims):
+        ref, _, _, _ = oracle_run(s, nt)
+        err = rel_l1(b.get_psi(i), ref)
+        print(f"layout {staged} sim {i} rel-L1 {err:.3e}")
+        assert err <= 1e-5, (i, err)
