@@ -684,6 +684,8 @@ __global__ void wake_split_kernel(int n, const double *__restrict__ wl64, double
     split[2 * n - 1 + idx] = l;
 }
 
+constexpr int kWakePer = 16;      // column sums per thread held in registers: n <= 4096
+
 template <bool FP16>
 __global__ __launch_bounds__(kThreads) void wake_mfma2_kernel(const SimDev *__restrict__ sims,
                                                               const WakeTile *__restrict__ tiles, int parity)
@@ -720,34 +722,43 @@ __global__ __launch_bounds__(kThreads) void wake_mfma2_kernel(const SimDev *__re
         c0h[y] = ok0 ? h : (uint16_t)0;
         c0l[y] = ok0 ? l : (uint16_t)0;
     }
-    double part = 0.0, mx = 0.0;
-#pragma unroll 8
-    for (int k = tid; k < n; k += kThreads) {
-        const double v = cs[k];
-        part += v;
-        mx = fmax(mx, fabs(v));
+    // rho entries outside the grid are zero
+    for (int k = tid; k < NR; k += kThreads) {
+        const int g = 16 * Jlo + k;
+        if (g < 0 || g >= n) { rhi[k] = 0; rlo[k] = 0; }
     }
-    part = block_sum(part, red);
+    // column sums: each thread loads its share once (n <= kWakePer * kThreads)
+    double v[kWakePer];
+    double part = 0.0, mx = 0.0;
+#pragma unroll
+    for (int q = 0; q < kWakePer; ++q) {
+        const int k = tid + q * kThreads;
+        v[q] = k < n ? cs[k] : 0.0;
+        part += v[q];
+        mx = fmax(mx, fabs(v[q]));
+    }
+    part = wave_sum(part);
     for (int off = 32; off > 0; off >>= 1) mx = fmax(mx, __shfl_xor(mx, off, 64));
-    if (lane == 0) red[wv] = mx;
+    if (lane == 0) { red[wv] = part; red[kWaves + wv] = mx; }
     __syncthreads();
-    mx = red[0];
-    for (int k = 1; k < kWaves; ++k) mx = fmax(mx, red[k]);
+    part = red[0];
+    mx = red[kWaves];
+    for (int k = 1; k < kWaves; ++k) { part += red[k]; mx = fmax(mx, red[kWaves + k]); }
     const double Qh = part * sd.dq * sd.dp;
     const double s = sd.renorm ? sd.Q0 / Qh : 1.0;
     const double rmax = mx * s * sd.dp;
     int e = 0;
     if (FP16 && rmax > 0.0) { frexp(rmax, &e); e = 14 - e; }
     const double rscale = ldexp(s * sd.dp, e);
-#pragma unroll 8
-    for (int k = tid; k < NR; k += kThreads) {
-        const int g = 16 * Jlo + k;
-        const bool ok = g >= 0 && g < n;
-        const double v = cs[ok ? g : 0];
-        uint16_t h, l;
-        split16<FP16>((float)((ok ? v : 0.0) * rscale), h, l);
-        rhi[k] = h;
-        rlo[k] = l;
+#pragma unroll
+    for (int q = 0; q < kWakePer; ++q) {
+        const int g = tid + q * kThreads, k = g - 16 * Jlo;
+        if (g < n && k >= 0 && k < NR) {
+            uint16_t h, l;
+            split16<FP16>((float)(v[q] * rscale), h, l);
+            rhi[k] = h;
+            rlo[k] = l;
+        }
     }
     __syncthreads();
     // copy 1 is copy 0 shifted by one lag

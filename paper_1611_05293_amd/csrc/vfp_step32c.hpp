@@ -142,6 +142,7 @@ __global__ __launch_bounds__(kThreads) void step32c_kernel(const SimDev *__restr
     __shared__ int sh_km[kMaxStripC];
     __shared__ float sh_rw[kMaxStripC][4];
     __shared__ int sh_rm[kMaxStripC];
+    __shared__ float2 sh_xy[kMaxStripC];       // per column: ax0 + i*axi, cy0 + i*cyi
     constexpr int o0 = (K - 1) / 2;
 
     const Unit u = units[xcd_unit(blockIdx.x, nunits)];
@@ -197,6 +198,8 @@ __global__ __launch_bounds__(kThreads) void step32c_kernel(const SimDev *__restr
         if (tid < W) shift = (double)sd.vext[i0 + tid] * sd.kick;
     }
     if (tid < W) {
+        const double ic = (double)(i0 + tid);
+        sh_xy[tid] = make_float2((float)fma(ic, sd.axi, sd.ax0), (float)fma(ic, sd.cyi, sd.cy0));
         const double fl = floor(shift);
         float l[K];
         lagrange_fma<K>((float)(shift - fl), l);
@@ -262,9 +265,8 @@ __global__ __launch_bounds__(kThreads) void step32c_kernel(const SimDev *__restr
         if constexpr (ROT == 0) {
             const float bxf = sd.fbx, byf = sd.fby;
             for (int c = wv; c < W; c += kWaves) {
-                const double ic = (double)(i0 + c);
-                const float Xc = (float)fma(ic, sd.axi, sd.ax0);
-                const float Yc = (float)fma(ic, sd.cyi, sd.cy0);
+                const float2 xy = sh_xy[c];
+                const float Xc = xy.x, Yc = xy.y;
                 // LDS byte address of the stencil corner for zero displacement
                 const int cb4 = (int)lds_addr(S + (c + kH - o0) * SY + lane + 4 - o0);
                 float *acol = A + c * LA + kPad + j0 + lane;
