@@ -157,7 +157,7 @@ size_t layout(const vfp_params *p, int count, std::vector<HostSim> *hs)
         h.off_wl64 = off; off = align_up(off + (2 * n - 1) * 8);
         h.off_wl32 = off; off = align_up(off + (2 * n - 1) * 4);
         h.off_frag = off;
-        if (q.precision >= VFP_MIXED_BF16) off = align_up(off + (size_t)(2 * n - 1) * 2 * sizeof(uint16_t));
+        if (q.precision >= VFP_MIXED_BF16) off = align_up(off + (size_t)4 * wake_rev_len(q.n) * sizeof(uint16_t));
         h.off_vext = off; off = align_up(off + n * 4);
         h.off_sext = off; off = align_up(off + 2 * 8);
         h.off_rho = off; off = align_up(off + n * 8);
@@ -215,6 +215,20 @@ struct vfp_batch {
     std::vector<WakeTile> wtiles;
     WakeTile *d_wtiles = nullptr;
     size_t wtiles_cap = 0;
+    // stream groups: the active simulations split in two halves (by cells), each
+    // advanced on its own stream so that one half's wake overlaps the other's step
+    int lanes = 2;                 // tuning: 1 or 2 groups
+    int ngroups = 1;               // groups in use (1 for a single simulation or while timing)
+    size_t unit_off[2] = {0, 0}, unit_cnt[2] = {0, 0}, tile_off[2] = {0, 0}, tile_cnt[2] = {0, 0};
+    hipStream_t stream2 = nullptr;
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+    bool forked = false;
+    // launch target of the group being launched
+    const Unit *cur_units = nullptr;
+    int cur_nunits = 0;
+    const WakeTile *cur_tiles = nullptr;
+    int cur_ntiles = 0;
+    hipStream_t cur_stream = nullptr;
     // per-kernel event timing (direct launches while enabled)
     bool timing = false;
     std::vector<hipEvent_t> ev_pool;
@@ -251,13 +265,31 @@ int rebuild_units(vfp_batch *b)
     for (int s = 0; s < b->count; ++s)
         if (b->hs[s].active) b->active.push_back(s);
     b->units.clear();
-    for (int s : b->active) {
-        const int n = b->hs[s].p.n;
-        const int w = b->staged == 3 ? choose_strip_c(n, b->cells, b->rotation) : choose_strip(n, b->cells);
-        const int o0 = (b->K - 1) / 2;
-        const int SY = b->staged == 2 ? (n >= 256 ? 256 : (n + 63) / 64 * 64) + 2 * kH : kSY;
-        for (int i0 = 0; i0 < n; i0 += w)
-            b->units.push_back(Unit{s, i0, std::min(w, n - i0), (kH - o0) * (SY + 1)});
+    // groups: balance the cells of the active simulations over the streams
+    b->ngroups = (b->lanes == 2 && b->active.size() >= 2 && !b->timing) ? 2 : 1;
+    std::vector<int> group(b->count, 0);
+    if (b->ngroups == 2) {
+        std::vector<int> order(b->active);
+        std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return b->hs[x].p.n > b->hs[y].p.n; });
+        double load[2] = {0.0, 0.0};
+        for (int s : order) {
+            const int g = load[1] < load[0] ? 1 : 0;
+            group[s] = g;
+            load[g] += (double)b->hs[s].p.n * b->hs[s].p.n;
+        }
+    }
+    for (int g = 0; g < b->ngroups; ++g) {
+        b->unit_off[g] = b->units.size();
+        for (int s : b->active) {
+            if (group[s] != g) continue;
+            const int n = b->hs[s].p.n;
+            const int w = b->staged == 3 ? choose_strip_c(n, b->cells, b->rotation) : choose_strip(n, b->cells);
+            const int o0 = (b->K - 1) / 2;
+            const int SY = b->staged == 2 ? (n >= 256 ? 256 : (n + 63) / 64 * 64) + 2 * kH : kSY;
+            for (int i0 = 0; i0 < n; i0 += w)
+                b->units.push_back(Unit{s, i0, std::min(w, n - i0), (kH - o0) * (SY + 1)});
+        }
+        b->unit_cnt[g] = b->units.size() - b->unit_off[g];
     }
     if (b->units.size() > b->units_cap) {
         if (b->d_units) HIPCHK(hipFree(b->d_units));
@@ -297,17 +329,22 @@ int rebuild_units(vfp_batch *b)
     b->wtiles.clear();
     b->lds_wake = 0;
     if (b->precision >= VFP_MIXED_BF16) {
+      for (int g = 0; g < b->ngroups; ++g) {
+        b->tile_off[g] = b->wtiles.size();
         for (int s : b->active) {
+            if (group[s] != g) continue;
             const int nb = (b->hs[s].p.n + 15) / 16;
             for (int t = 0; t < (nb + 15) / 16; ++t) {
                 b->wtiles.push_back(WakeTile{s, t, 0, 0});
                 const int I0 = 16 * t;
                 const int dmin = std::max(-(nb - 1), I0 - (nb - 1)), dmax = std::min(nb - 1, I0 + 15);
                 const size_t NR = 16 * (16 + dmax - dmin), NL = 16 * (dmax - dmin) + 31;
-                const size_t NLp = (NL + 1 + 3) & ~(size_t)3;
+                const size_t NLp = (NL + 1 + 7) & ~(size_t)7;
                 b->lds_wake = std::max(b->lds_wake, (2 * NR + 4 * NLp) * sizeof(uint16_t));
             }
         }
+        b->tile_cnt[g] = b->wtiles.size() - b->tile_off[g];
+      }
         if (b->wtiles.size() > b->wtiles_cap) {
             if (b->d_wtiles) HIPCHK(hipFree(b->d_wtiles));
             b->d_wtiles = nullptr;
@@ -331,8 +368,8 @@ void launch_step_t(vfp_batch *b, int parity)
     auto k = step_kernel<T, K, WAKE, CL, ROT>;
     static int cur = 0;
     lds_limit(k, b->lds_step, cur);
-    hipLaunchKernelGGL(k, dim3((unsigned)b->units.size()), dim3(kThreads), b->lds_step, b->stream,
-                       b->d_sd, b->d_units, (int)b->units.size(), parity);
+    hipLaunchKernelGGL(k, dim3((unsigned)b->cur_nunits), dim3(kThreads), b->lds_step, b->cur_stream,
+                       b->d_sd, b->cur_units, b->cur_nunits, parity);
 }
 
 template <int K, int WAKE, bool CL, int ROT>
@@ -343,8 +380,8 @@ void launch_step32_t(vfp_batch *b, int parity)
                               : step32_kernel<K, WAKE, CL, ROT>;
     static int cur[4] = {0, 0, 0, 0};
     lds_limit(k, b->lds_step, cur[b->staged]);
-    hipLaunchKernelGGL(k, dim3((unsigned)b->units.size()), dim3(kThreads), b->lds_step, b->stream,
-                       b->d_sd, b->d_units, (int)b->units.size(), parity);
+    hipLaunchKernelGGL(k, dim3((unsigned)b->cur_nunits), dim3(kThreads), b->lds_step, b->cur_stream,
+                       b->d_sd, b->cur_units, b->cur_nunits, parity);
 }
 
 template <typename T, int K, int WAKE>
@@ -396,9 +433,10 @@ int timing_event(vfp_batch *b, int *idx)
     return VFP_OK;
 }
 
-int launch_tick(vfp_batch *b, int parity)
+// the kernels of one tick for the group selected by select_group()
+int launch_tick_group(vfp_batch *b, int parity)
 {
-    if (b->units.empty()) return VFP_OK;
+    if (b->cur_nunits == 0) return VFP_OK;
     const bool wake = any_wake(b);
     int t0 = -1, t1 = -1, t2 = -1;
     const bool mfma = b->precision >= VFP_MIXED_BF16 && wake;
@@ -417,8 +455,9 @@ int launch_tick(vfp_batch *b, int parity)
         auto wk = fp16 ? wake_mfma2_kernel<true> : wake_mfma2_kernel<false>;
         static int cur16 = 0, cur8 = 0;
         lds_limit(wk, b->lds_wake, fp16 ? cur16 : cur8);
-        hipLaunchKernelGGL(wk, dim3((unsigned)b->wtiles.size()), dim3(kThreads), b->lds_wake, b->stream,
-                           b->d_sd, b->d_wtiles, parity);
+        if (b->cur_ntiles > 0)
+            hipLaunchKernelGGL(wk, dim3((unsigned)b->cur_ntiles), dim3(kThreads), b->lds_wake, b->cur_stream,
+                               b->d_sd, b->cur_tiles, parity);
         if (b->timing) {
             int rc = timing_event(b, &t1);
             if (rc) return rc;
@@ -437,6 +476,47 @@ int launch_tick(vfp_batch *b, int parity)
         }
     }
     return VFP_OK;
+}
+
+void select_group(vfp_batch *b, int g)
+{
+    b->cur_units = b->d_units + b->unit_off[g];
+    b->cur_nunits = (int)b->unit_cnt[g];
+    b->cur_tiles = b->d_wtiles ? b->d_wtiles + b->tile_off[g] : nullptr;
+    b->cur_ntiles = (int)b->tile_cnt[g];
+    b->cur_stream = g == 0 ? b->stream : b->stream2;
+}
+
+// the second stream starts after the work already queued on the batch's stream
+int fork_streams(vfp_batch *b)
+{
+    if (b->ngroups < 2 || b->forked) return VFP_OK;
+    HIPCHK(hipEventRecord(b->ev_fork, b->stream));
+    HIPCHK(hipStreamWaitEvent(b->stream2, b->ev_fork, 0));
+    b->forked = true;
+    return VFP_OK;
+}
+
+// the batch's stream continues after the second stream's work
+int join_streams(vfp_batch *b)
+{
+    if (!b->forked) return VFP_OK;
+    HIPCHK(hipEventRecord(b->ev_join, b->stream2));
+    HIPCHK(hipStreamWaitEvent(b->stream, b->ev_join, 0));
+    b->forked = false;
+    return VFP_OK;
+}
+
+// one tick of every group (forks the second stream if needed; does not join)
+int launch_tick(vfp_batch *b, int parity)
+{
+    if (b->units.empty()) return VFP_OK;
+    int rc = fork_streams(b);
+    for (int g = 0; g < b->ngroups && rc == VFP_OK; ++g) {
+        select_group(b, g);
+        rc = launch_tick_group(b, parity);
+    }
+    return rc;
 }
 
 // stats over an explicit list of (simulation, buffer) pairs
@@ -498,6 +578,7 @@ int check_finite(vfp_batch *b, int s)
 int direct_tick(vfp_batch *b)
 {
     int rc = launch_tick(b, b->parity);
+    if (rc == VFP_OK) rc = join_streams(b);
     if (rc) return rc;
     if (b->every > 0 && ((b->tick + 1 - b->rec_base) % b->every) == 0) rc = launch_record(b, b->parity);
     return rc;
@@ -513,10 +594,14 @@ int capture_graph(vfp_batch *b, int G)
     int rc = VFP_OK;
     for (int t = 0; t < G && rc == VFP_OK; ++t) {
         rc = launch_tick(b, par);
-        if (rc == VFP_OK && b->every > 0 && ((b->tick + t + 1 - b->rec_base) % b->every) == 0)
-            rc = launch_record(b, par);
+        if (rc == VFP_OK && b->every > 0 && ((b->tick + t + 1 - b->rec_base) % b->every) == 0) {
+            rc = join_streams(b);
+            if (rc == VFP_OK) rc = launch_record(b, par);
+        }
         par ^= 1;
     }
+    if (rc == VFP_OK) rc = join_streams(b);
+    b->forked = false;
     hipGraph_t g = nullptr;
     const hipError_t e = hipStreamEndCapture(b->stream, &g);
     if (rc) { if (g) (void)hipGraphDestroy(g); return rc; }
@@ -603,6 +688,12 @@ void free_batch(vfp_batch *b)
     if (b->d_ring_rows) (void)hipFree(b->d_ring_rows);
     if (b->d_stage) (void)hipFree(b->d_stage);
     for (hipEvent_t e : b->ev_pool) (void)hipEventDestroy(e);
+    if (b->stream2) {
+        (void)hipStreamSynchronize(b->stream2);
+        (void)hipStreamDestroy(b->stream2);
+    }
+    if (b->ev_fork) (void)hipEventDestroy(b->ev_fork);
+    if (b->ev_join) (void)hipEventDestroy(b->ev_join);
     if (b->own_stream) (void)hipStreamDestroy(b->stream);
     delete b;
 }
@@ -699,6 +790,12 @@ int create_impl(const vfp_params *p, int32_t count, void *stream, void *ws, size
             return fail(VFP_EDEVICE, "stream creation failed");
         }
         b->own_stream = true;
+    }
+    if (hipStreamCreateWithFlags(&b->stream2, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&b->ev_fork, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&b->ev_join, hipEventDisableTiming) != hipSuccess) {
+        free_batch(b);
+        return fail(VFP_EDEVICE, "stream creation failed");
     }
     b->hs.resize(count);
     for (int s = 0; s < count; ++s) {
@@ -861,7 +958,7 @@ int create_impl(const vfp_params *p, int32_t count, void *stream, void *ws, size
                 e = 14 - e;
             }
             const double wscale = std::ldexp(1.0, e), wback = std::ldexp(1.0, -e);
-            const unsigned fb = (unsigned)((2 * n - 1 + kThreads - 1) / kThreads);
+            const unsigned fb = (unsigned)((wake_rev_len(n) + kThreads - 1) / kThreads);
             if (b->precision == VFP_MIXED_FP16)
                 hipLaunchKernelGGL(wake_split_kernel<true>, dim3(fb), dim3(kThreads), 0, b->stream, n,
                                    (const double *)(b->arena + h.off_wl64), wscale, (uint16_t *)(b->arena + h.off_frag));
@@ -1145,6 +1242,25 @@ int vfp_batch_set_tuning(vfp_batch *b, int32_t cells_per_unit, int32_t use_graph
     return VFP_OK;
 }
 
+#ifdef VFP_WAKE_PROBE
+extern "C" int vfp_batch_debug_vout(vfp_batch *b, int32_t i, double *out)
+{
+    HIPCHK(hipStreamSynchronize(b->stream));
+    HIPCHK(hipMemcpy(out, b->sd[i].v_out, sizeof(double) * b->hs[i].p.n, hipMemcpyDeviceToHost));
+    return VFP_OK;
+}
+#endif
+
+int vfp_batch_set_streams(vfp_batch *b, int32_t groups)
+{
+    if (!b || (groups != 1 && groups != 2)) return fail(VFP_EINVAL, "groups must be 1 or 2");
+    HIPCHK(hipStreamSynchronize(b->stream));
+    b->lanes = groups;
+    b->units_dirty = true;
+    b->graph_valid = false;
+    return VFP_OK;
+}
+
 int vfp_batch_get_tuning(vfp_batch *b, int32_t *cells_per_unit, int32_t *use_graph, int32_t *staged)
 {
     if (!b) return fail(VFP_EINVAL, "invalid arguments");
@@ -1264,6 +1380,8 @@ int vfp_batch_kernel_timing(vfp_batch *b, int32_t enable)
     b->ev_step.clear();
     b->ev_wake.clear();
     b->timing = enable != 0;
+    b->units_dirty = true;        // one stream group while timing
+    b->graph_valid = false;
     return VFP_OK;
 }
 

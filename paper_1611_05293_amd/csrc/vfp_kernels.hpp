@@ -42,7 +42,7 @@ struct SimDev {
     double *colsum[2];
     const double *wl64;              // 2n-1 lags, FP64
     const float *wl32;               // 2n-1 lags, FP32
-    const uint16_t *wsplit;          // matrix-core wake: hi then lo 16-bit parts of the scaled lags
+    const uint16_t *wsplit;          // matrix-core wake: reversed hi/lo lag tables (wake_split_kernel)
     float *vext;                     // wake used by the latest step (n, FP32)
     double *sext;                    // renormalisation factor used with vext
     double *rho_out, *v_out;         // FP64 diagnostics (n each)
@@ -672,19 +672,41 @@ struct WakeTile {
     int32_t sim, tile, pad0, pad1;
 };
 
-// split[lag + n - 1] = hi, split[(2n-1) + lag + n - 1] = lo of w[lag] * wscale
+// Lag tables of the matrix-core wake, made once at set-up: four arrays of
+// wake_rev_len(n) 16-bit values, the hi and lo parts of w[lag] * wscale in
+// reversed lag order (entry P + k holds lag n - 1 - k, k = 0 .. 2n-2; zero
+// elsewhere), and the same two arrays shifted by one entry.  A tile's lag
+// window is then one contiguous, 16-byte aligned run of each array.
+__host__ __device__ inline int wake_rev_pad(int n) { return 16 + ((8 - (n & 7)) & 7); }
+__host__ __device__ inline int wake_rev_len(int n) { return (wake_rev_pad(n) + 2 * n + 24 + 7) & ~7; }
+
 template <bool FP16>
 __global__ void wake_split_kernel(int n, const double *__restrict__ wl64, double wscale, uint16_t *__restrict__ split)
 {
+    const int LW = wake_rev_len(n), P = wake_rev_pad(n);
     const int idx = blockIdx.x * kThreads + threadIdx.x;
-    if (idx >= 2 * n - 1) return;
-    uint16_t h, l;
-    split16<FP16>((float)(wl64[idx] * wscale), h, l);
-    split[idx] = h;
-    split[2 * n - 1 + idx] = l;
+    if (idx >= LW) return;
+    uint16_t h[2] = {0, 0}, l[2] = {0, 0};
+    for (int sft = 0; sft < 2; ++sft) {
+        const int k = idx + sft - P;                    // reversed position: lag n - 1 - k
+        if (k >= 0 && k <= 2 * n - 2) split16<FP16>((float)(wl64[2 * n - 2 - k] * wscale), h[sft], l[sft]);
+    }
+    split[idx] = h[0];
+    split[LW + idx] = l[0];
+    split[2 * LW + idx] = h[1];
+    split[3 * LW + idx] = l[1];
 }
 
 constexpr int kWakePer = 16;      // column sums per thread held in registers: n <= 4096
+
+#ifdef VFP_WAKE_PROBE
+#define VFP_WAKE_MARK(k)                                                                      \
+    do {                                                                                      \
+        if (tid == 0) sd.v_out[8 * wt.tile + (k)] = (double)wall_clock64();                   \
+    } while (0)
+#else
+#define VFP_WAKE_MARK(k) do { } while (0)
+#endif
 
 template <bool FP16>
 __global__ __launch_bounds__(kThreads) void wake_mfma2_kernel(const SimDev *__restrict__ sims,
@@ -703,37 +725,45 @@ __global__ __launch_bounds__(kThreads) void wake_mfma2_kernel(const SimDev *__re
     const int NR = 16 * (16 + dmax - dmin);            // rho entries of block columns Jlo..Jhi
     const int Lhi = 16 * dmax + 15;                     // highest lag used
     const int NL = 16 * (dmax - dmin) + 31;             // lags Lhi-NL+1 .. Lhi
-    const int NLp = (NL + 1 + 3) & ~3;
+    const int NLp = (NL + 1 + 7) & ~7;                  // staged entries per copy (16-byte runs)
     uint16_t *rhi = (uint16_t *)smem_raw;
     uint16_t *rlo = rhi + NR;
     uint16_t *c0h = rlo + NR, *c0l = c0h + NLp, *c1h = c0l + NLp, *c1l = c1h + NLp;
     typedef const __attribute__((address_space(1))) double gdouble;
     typedef const __attribute__((address_space(1))) uint16_t gu16;
     gdouble *cs = (gdouble *)sd.colsum[parity];
+    VFP_WAKE_MARK(0);
 
-    // lag range, copy 0 (branch-free loads, so the unrolled loop issues them together)
-    gu16 *wh = (gu16 *)sd.wsplit, *wlo = (gu16 *)(sd.wsplit + (2 * n - 1));
-#pragma unroll 8
-    for (int y = tid; y < NL + 1; y += kThreads) {
-        const int L0 = Lhi - y;
-        const bool ok0 = L0 > -n && L0 < n && y < NL;
-        const int ix = ok0 ? L0 + n - 1 : 0;
-        const uint16_t h = wh[ix], l = wlo[ix];
-        c0h[y] = ok0 ? h : (uint16_t)0;
-        c0l[y] = ok0 ? l : (uint16_t)0;
+    // column sums: each thread loads its share once (n <= kWakePer * kThreads);
+    // issued first so their latency overlaps the lag staging below
+    double v[kWakePer];
+#pragma unroll
+    for (int q = 0; q < kWakePer; ++q) {
+        const int k = tid + q * kThreads;
+        v[q] = k < n ? cs[k] : 0.0;
     }
+    // lag window: copy 0 (entry y = lag Lhi - y) and copy 1 (shifted by one),
+    // hi and lo, each one aligned run of the reversed tables
+    {
+        const int LW = wake_rev_len(n), st0 = wake_rev_pad(n) + n - 1 - Lhi;   // st0 % 8 == 0
+        typedef unsigned int v4u __attribute__((ext_vector_type(4)));
+        typedef const __attribute__((address_space(1))) v4u gv4u;
+        const int q8 = NLp / 8;
+        for (int k = tid; k < 4 * q8; k += kThreads) {
+            const int arr = k / q8, q = k - arr * q8;
+            const v4u v = *(gv4u *)(sd.wsplit + (size_t)arr * LW + st0 + 8 * q);
+            *(v4u *)(c0h + (size_t)arr * NLp + 8 * q) = v;
+        }
+    }
+    VFP_WAKE_MARK(1);
     // rho entries outside the grid are zero
     for (int k = tid; k < NR; k += kThreads) {
         const int g = 16 * Jlo + k;
         if (g < 0 || g >= n) { rhi[k] = 0; rlo[k] = 0; }
     }
-    // column sums: each thread loads its share once (n <= kWakePer * kThreads)
-    double v[kWakePer];
     double part = 0.0, mx = 0.0;
 #pragma unroll
     for (int q = 0; q < kWakePer; ++q) {
-        const int k = tid + q * kThreads;
-        v[q] = k < n ? cs[k] : 0.0;
         part += v[q];
         mx = fmax(mx, fabs(v[q]));
     }
@@ -744,6 +774,7 @@ __global__ __launch_bounds__(kThreads) void wake_mfma2_kernel(const SimDev *__re
     part = red[0];
     mx = red[kWaves];
     for (int k = 1; k < kWaves; ++k) { part += red[k]; mx = fmax(mx, red[kWaves + k]); }
+    VFP_WAKE_MARK(2);
     const double Qh = part * sd.dq * sd.dp;
     const double s = sd.renorm ? sd.Q0 / Qh : 1.0;
     const double rmax = mx * s * sd.dp;
@@ -761,13 +792,7 @@ __global__ __launch_bounds__(kThreads) void wake_mfma2_kernel(const SimDev *__re
         }
     }
     __syncthreads();
-    // copy 1 is copy 0 shifted by one lag
-    for (int y = tid; y < NL + 1; y += kThreads) {
-        const bool ok = y + 1 <= NL;
-        c1h[y] = ok ? c0h[y + 1] : (uint16_t)0;
-        c1l[y] = ok ? c0l[y + 1] : (uint16_t)0;
-    }
-    __syncthreads();
+    VFP_WAKE_MARK(3);
 
     const int a = lane & 15, kq = 4 * (lane >> 4);
     // y0 = Lhi - (16d + a - kq) for d = dmax is 15 - a + kq; even y0 read copy 0 at y0,
@@ -777,13 +802,21 @@ __global__ __launch_bounds__(kThreads) void wake_mfma2_kernel(const SimDev *__re
     const uint16_t *ah = odd ? c1h + (y00 - 1) : c0h + y00;
     const uint16_t *al = odd ? c1l + (y00 - 1) : c0l + y00;
     v4f acc0 = {0.0f, 0.0f, 0.0f, 0.0f}, acc1 = acc0, acc2 = acc0;
-    for (int d = dmax - wv; d >= dmin; d -= kWaves) {
+    // fragments of block diagonal d, loaded one iteration ahead of their use
+    auto frag = [&](int d, uint2 &A_h, uint2 &A_l, uint2 &B_h, uint2 &B_l) {
         const int yo = 16 * (dmax - d);
-        const uint2 A_h = make_uint2(*(const uint32_t *)(ah + yo), *(const uint32_t *)(ah + yo + 2));
-        const uint2 A_l = make_uint2(*(const uint32_t *)(al + yo), *(const uint32_t *)(al + yo + 2));
+        A_h = make_uint2(*(const uint32_t *)(ah + yo), *(const uint32_t *)(ah + yo + 2));
+        A_l = make_uint2(*(const uint32_t *)(al + yo), *(const uint32_t *)(al + yo + 2));
         const int bidx = 16 * (I0 + a - d - Jlo) + kq;
-        const uint2 B_h = *(const uint2 *)(rhi + bidx);
-        const uint2 B_l = *(const uint2 *)(rlo + bidx);
+        B_h = *(const uint2 *)(rhi + bidx);
+        B_l = *(const uint2 *)(rlo + bidx);
+    };
+    int d = dmax - wv;
+    uint2 A_h, A_l, B_h, B_l;
+    if (d >= dmin) frag(d, A_h, A_l, B_h, B_l);
+    for (; d >= dmin; d -= kWaves) {
+        uint2 nA_h = A_h, nA_l = A_l, nB_h = B_h, nB_l = B_l;
+        if (d - kWaves >= dmin) frag(d - kWaves, nA_h, nA_l, nB_h, nB_l);
         if constexpr (FP16) {
             acc0 = __builtin_amdgcn_mfma_f32_16x16x16f16(__builtin_bit_cast(v4h, A_h), __builtin_bit_cast(v4h, B_h), acc0, 0, 0, 0);
             acc1 = __builtin_amdgcn_mfma_f32_16x16x16f16(__builtin_bit_cast(v4h, A_h), __builtin_bit_cast(v4h, B_l), acc1, 0, 0, 0);
@@ -793,7 +826,9 @@ __global__ __launch_bounds__(kThreads) void wake_mfma2_kernel(const SimDev *__re
             acc1 = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(__builtin_bit_cast(v4s, A_h), __builtin_bit_cast(v4s, B_l), acc1, 0, 0, 0);
             acc2 = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(__builtin_bit_cast(v4s, A_l), __builtin_bit_cast(v4s, B_h), acc2, 0, 0, 0);
         }
+        A_h = nA_h; A_l = nA_l; B_h = nB_h; B_l = nB_l;
     }
+    VFP_WAKE_MARK(4);
     double t[4];
     for (int q = 0; q < 4; ++q) t[q] = (double)acc0[q] + ((double)acc1[q] + (double)acc2[q]);
     if (wv > 0)
@@ -809,6 +844,7 @@ __global__ __launch_bounds__(kThreads) void wake_mfma2_kernel(const SimDev *__re
         }
         if (wt.tile == 0 && lane == 0) sd.sext[0] = s;
     }
+    VFP_WAKE_MARK(5);
 }
 
 // CSR spectrum of the state whose profile the diagnostics kernel left in

@@ -176,14 +176,25 @@ __global__ __launch_bounds__(kThreads) void step32c_kernel(const SimDev *__restr
         const int c = tid / parts, pt = tid - c * parts;
         double acc = 0.0;
         if (c < W) {
-            const int i = i0 + c;
-            float a32 = 0.0f;
-            int cnt = 0;
-            for (int j = pt; j < n; j += parts) {
-                a32 = fmaf(sd.wl32[i - j + n - 1], (float)(sd.dp * cs[j]), a32);
-                if (++cnt == 32) { acc += a32; a32 = 0.0f; cnt = 0; }
+            // FP32 partial sums over blocks of 32 of this thread's terms, added in FP64;
+            // the unrolled block lets the loads of several terms be in flight together
+            typedef const __attribute__((address_space(1))) float gfloat;
+            typedef const __attribute__((address_space(1))) double gdouble;
+            gfloat *wl = (gfloat *)sd.wl32 + (i0 + c) + n - 1;
+            gdouble *gcs = (gdouble *)cs;
+            const double dp = sd.dp;
+            for (int jb = pt; jb < n; jb += 32 * parts) {
+                float a32 = 0.0f;
+                for (int q0 = 0; q0 < 32 && jb + q0 * parts < n; q0 += 8) {
+#pragma unroll
+                    for (int q = q0; q < q0 + 8; ++q) {
+                        const int j = jb + q * parts, jj = j < n ? j : n - 1;   // loads stay in bounds
+                        const float t = fmaf(wl[-jj], (float)(dp * gcs[jj]), a32);
+                        a32 = j < n ? t : a32;
+                    }
+                }
+                acc += a32;
             }
-            acc += a32;
         }
         __syncthreads();
         red[tid] = acc;

@@ -95,6 +95,7 @@ def load():
             "vfp_batch_destroy": (None, [h]),
             "vfp_batch_set_tuning": (C.c_int, [h, C.c_int32, C.c_int32, C.c_int32]),
             "vfp_batch_get_tuning": (C.c_int, [h, C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.POINTER(C.c_int32)]),
+            "vfp_batch_set_streams": (C.c_int, [h, C.c_int32]),
             "vfp_batch_autotune": (C.c_int, [h, C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]),
             "vfp_device_arch": (C.c_int, [C.c_char_p, C.c_int32]),
             "vfp_batch_kernel_timing": (C.c_int, [h, C.c_int32]),
@@ -249,6 +250,10 @@ class Batch:
 
     def set_tuning(self, cells_per_unit: int = 0, use_graph: bool = True, staged: int = 3):
         _check(load().vfp_batch_set_tuning(self._h, int(cells_per_unit), int(bool(use_graph)), int(staged)))
+
+    def set_streams(self, groups: int):
+        """1: every simulation on the batch's stream; 2: two halves on two streams."""
+        _check(load().vfp_batch_set_streams(self._h, int(groups)))
 
     def get_tuning(self) -> tuple:
         """(cells per unit, graph replay, kernel layout) in force."""

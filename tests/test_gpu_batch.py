@@ -209,3 +209,23 @@ def test_strong_kick_every_read_path(staged):
         err = rel_l1(b.get_psi(i), ref)
         print(f"layout {staged} sim {i} rel-L1 {err:.3e}")
         assert err <= 1e-5, (i, err)
+
+
+@pytest.mark.parametrize("precision", ["fp16", "fp32"])
+def test_two_stream_groups_equal_one(precision):
+    """The two-stream split of a batch gives bit-identical states and records
+    to advancing every simulation on one stream (graph replay and direct)."""
+    sims = mixed_sims()
+    out = []
+    for groups, graph in ((1, True), (2, True), (2, False)):
+        b = vfp.Batch([vfp.sim_kwargs(s, precision=precision) for s in sims])
+        b.set_tuning(0, graph, 3)
+        b.set_streams(groups)
+        b.record(5, 20)
+        b.step(37)
+        out.append(([b.get_psi(i) for i in range(len(sims))], [b.read_record(i) for i in range(len(sims))]))
+        b.close()
+    for psis, recs in out[1:]:
+        for i in range(len(sims)):
+            assert np.array_equal(psis[i], out[0][0][i])
+            assert np.array_equal(recs[i], out[0][1][i])
