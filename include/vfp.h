@@ -185,7 +185,7 @@ void vfp_batch_destroy(vfp_batch *b);
  * into the damping pass, 3 the staged kernel with 192-row chunks, 16-byte
  * staging, FP32 source displacements and per-row damping coefficients
  * (same arithmetic definition, different evaluation order; returns
- * VFP_EINVAL for other values).  A new batch uses cells_per_unit 4096,
+ * VFP_EINVAL for other values).  A new batch uses cells_per_unit 8192,
  * graph replay and layout 3. */
 int vfp_batch_set_tuning(vfp_batch *b, int32_t cells_per_unit, int32_t use_graph, int32_t staged);
 

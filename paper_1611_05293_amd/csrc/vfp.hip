@@ -82,7 +82,10 @@ int choose_strip(int n, int cells)
 // chunk keeps every staged column of a wave in the prefetch registers.
 // The dynamic LDS of a unit stays under kLdsBudgetC so that five workgroups
 // fit on a compute unit.
-constexpr size_t kLdsBudgetC = 28 * 1024;
+#ifndef VFP_LDS_BUDGET_KB
+#define VFP_LDS_BUDGET_KB 28
+#endif
+constexpr size_t kLdsBudgetC = VFP_LDS_BUDGET_KB * 1024;
 size_t lds_bytes_c(int n, int w, int rotation)
 {
     return ((size_t)w * (n + 2 * kPad) + (size_t)(w + 2 * kH) * kSYC + (rotation ? (size_t)w * kSYC : 0)) * 4;
@@ -781,7 +784,7 @@ int create_impl(const vfp_params *p, int32_t count, void *stream, void *ws, size
     b->K = p[0].interp;
     b->clamp = p[0].clamp;
     b->rotation = p[0].rotation;
-    b->cells = 4096;
+    b->cells = 8192;
     b->stream = (hipStream_t)stream;
     if (!b->stream) {
         // graphs cannot be captured on the null stream: use a stream of our own
@@ -1227,7 +1230,7 @@ void vfp_destroy(vfp_sim *sim) { free_batch(sim); }
 int vfp_batch_set_tuning(vfp_batch *b, int32_t cells_per_unit, int32_t use_graph, int32_t staged)
 {
     if (!b || cells_per_unit < 0) return fail(VFP_EINVAL, "invalid arguments");
-    const int def = 4096;
+    const int def = 8192;
     const int cells = cells_per_unit ? cells_per_unit : def;
     if (cells * elem_size(b->precision) * 2 > 128 * 1024)
         return fail(VFP_EINVAL, "cells_per_unit too large for the workgroup's LDS");

@@ -25,7 +25,10 @@
 
 namespace vfp {
 
-constexpr int kCH = 192;          // rows per chunk
+#ifndef VFP_CH
+#define VFP_CH 192
+#endif
+constexpr int kCH = VFP_CH;       // rows per chunk (a multiple of 64)
 constexpr int kSYC = kCH + 8;     // staged rows per column: j0-4 .. j0+kCH+3
 constexpr int kPF4 = 4;           // staged columns per wave held in registers across a chunk
 constexpr int kMaxStripC = 64;    // columns per work unit in this layout
@@ -46,57 +49,111 @@ __device__ __forceinline__ unsigned lds_addr(const void *p)
     return (unsigned)(uintptr_t)(const __attribute__((address_space(3))) void *)p;
 }
 
-// The K x K stencil taps f[a][b] = S[addr/4 + a*kSYC + b] of one lane, read at
-// immediate offsets from a single address: columns a = 0, 1 as paired reads
-// (dword offsets up to 203), a = 2, 3 as single reads (byte offsets from
-// 1600).  The compiler would otherwise form one base register per column.
-// The reads complete (lgkmcnt 0) before the asm ends.
-static_assert(kSYC == 200, "tap offsets below are written for 200-row staged columns");
-template <int K>
+// The K x K stencil taps f[a][b] = S[addr/4 + a*SY + b] of one lane, read at
+// immediate offsets from a single address: stencil column a = 0 (and a = 1
+// while its dword offsets stay below 256) as paired reads, the others as
+// single reads with byte offsets.  The compiler would otherwise form one base
+// register per stencil column.  The reads complete (lgkmcnt 0) before the asm
+// ends.
+template <int K, int SY>
 __device__ __forceinline__ void read_taps(unsigned addr, float (&f)[K][K])
 {
+    static_assert(12 * SY + 12 < 65536, "single-read byte offsets are 16 bits");
     if constexpr (K == 4) {
         f32x2 t0, t1, t2, t3;
         float u0, u1, u2, u3, u4, u5, u6, u7;
-        asm volatile(
-            "ds_read2_b32 %0, %12 offset1:1\n\t"
-            "ds_read2_b32 %1, %12 offset0:2 offset1:3\n\t"
-            "ds_read2_b32 %2, %12 offset0:200 offset1:201\n\t"
-            "ds_read2_b32 %3, %12 offset0:202 offset1:203\n\t"
-            "ds_read_b32 %4, %12 offset:1600\n\t"
-            "ds_read_b32 %5, %12 offset:1604\n\t"
-            "ds_read_b32 %6, %12 offset:1608\n\t"
-            "ds_read_b32 %7, %12 offset:1612\n\t"
-            "ds_read_b32 %8, %12 offset:2400\n\t"
-            "ds_read_b32 %9, %12 offset:2404\n\t"
-            "ds_read_b32 %10, %12 offset:2408\n\t"
-            "ds_read_b32 %11, %12 offset:2412\n\t"
-            "s_waitcnt lgkmcnt(0)"
-            : "=&v"(t0), "=&v"(t1), "=&v"(t2), "=&v"(t3), "=&v"(u0), "=&v"(u1), "=&v"(u2), "=&v"(u3),
-              "=&v"(u4), "=&v"(u5), "=&v"(u6), "=&v"(u7)
-            : "v"(addr));
+        if constexpr (SY + 3 <= 255) {
+            asm volatile(
+                "ds_read2_b32 %0, %12 offset1:1\n\t"
+                "ds_read2_b32 %1, %12 offset0:2 offset1:3\n\t"
+                "ds_read2_b32 %2, %12 offset0:%13 offset1:%14\n\t"
+                "ds_read2_b32 %3, %12 offset0:%15 offset1:%16\n\t"
+                "ds_read_b32 %4, %12 offset:%17\n\t"
+                "ds_read_b32 %5, %12 offset:%18\n\t"
+                "ds_read_b32 %6, %12 offset:%19\n\t"
+                "ds_read_b32 %7, %12 offset:%20\n\t"
+                "ds_read_b32 %8, %12 offset:%21\n\t"
+                "ds_read_b32 %9, %12 offset:%22\n\t"
+                "ds_read_b32 %10, %12 offset:%23\n\t"
+                "ds_read_b32 %11, %12 offset:%24\n\t"
+                "s_waitcnt lgkmcnt(0)"
+                : "=&v"(t0), "=&v"(t1), "=&v"(t2), "=&v"(t3), "=&v"(u0), "=&v"(u1), "=&v"(u2), "=&v"(u3),
+                  "=&v"(u4), "=&v"(u5), "=&v"(u6), "=&v"(u7)
+                : "v"(addr), "i"(SY), "i"(SY + 1), "i"(SY + 2), "i"(SY + 3), "i"(8 * SY), "i"(8 * SY + 4),
+                  "i"(8 * SY + 8), "i"(8 * SY + 12), "i"(12 * SY), "i"(12 * SY + 4), "i"(12 * SY + 8),
+                  "i"(12 * SY + 12));
+        } else {
+            float v0, v1, v2, v3;
+            asm volatile(
+                "ds_read2_b32 %0, %16 offset1:1\n\t"
+                "ds_read2_b32 %1, %16 offset0:2 offset1:3\n\t"
+                "ds_read_b32 %12, %16 offset:%17\n\t"
+                "ds_read_b32 %13, %16 offset:%18\n\t"
+                "ds_read_b32 %14, %16 offset:%19\n\t"
+                "ds_read_b32 %15, %16 offset:%20\n\t"
+                "ds_read_b32 %4, %16 offset:%21\n\t"
+                "ds_read_b32 %5, %16 offset:%22\n\t"
+                "ds_read_b32 %6, %16 offset:%23\n\t"
+                "ds_read_b32 %7, %16 offset:%24\n\t"
+                "ds_read_b32 %8, %16 offset:%25\n\t"
+                "ds_read_b32 %9, %16 offset:%26\n\t"
+                "ds_read_b32 %10, %16 offset:%27\n\t"
+                "ds_read_b32 %11, %16 offset:%28\n\t"
+                "s_waitcnt lgkmcnt(0)"
+                : "=&v"(t0), "=&v"(t1), "=&v"(t2), "=&v"(t3), "=&v"(u0), "=&v"(u1), "=&v"(u2), "=&v"(u3),
+                  "=&v"(u4), "=&v"(u5), "=&v"(u6), "=&v"(u7), "=&v"(v0), "=&v"(v1), "=&v"(v2), "=&v"(v3)
+                : "v"(addr), "i"(4 * SY), "i"(4 * SY + 4), "i"(4 * SY + 8), "i"(4 * SY + 12), "i"(8 * SY),
+                  "i"(8 * SY + 4), "i"(8 * SY + 8), "i"(8 * SY + 12), "i"(12 * SY), "i"(12 * SY + 4),
+                  "i"(12 * SY + 8), "i"(12 * SY + 12));
+            t2 = f32x2{v0, v1};
+            t3 = f32x2{v2, v3};
+        }
         f[0][0] = t0.x; f[0][1] = t0.y; f[0][2] = t1.x; f[0][3] = t1.y;
         f[1][0] = t2.x; f[1][1] = t2.y; f[1][2] = t3.x; f[1][3] = t3.y;
         f[2][0] = u0; f[2][1] = u1; f[2][2] = u2; f[2][3] = u3;
         f[3][0] = u4; f[3][1] = u5; f[3][2] = u6; f[3][3] = u7;
     } else {
-        f32x2 t0, t1;
-        float u0, u1, u2, u3, u4;
+        float u0, u1, u2, u3, u4, u5, u6;
+        f32x2 t0;
         asm volatile(
-            "ds_read2_b32 %0, %7 offset1:1\n\t"
-            "ds_read_b32 %2, %7 offset:8\n\t"
-            "ds_read2_b32 %1, %7 offset0:200 offset1:201\n\t"
-            "ds_read_b32 %3, %7 offset:808\n\t"
-            "ds_read_b32 %4, %7 offset:1600\n\t"
-            "ds_read_b32 %5, %7 offset:1604\n\t"
-            "ds_read_b32 %6, %7 offset:1608\n\t"
+            "ds_read2_b32 %0, %8 offset1:1\n\t"
+            "ds_read_b32 %1, %8 offset:8\n\t"
+            "ds_read_b32 %2, %8 offset:%9\n\t"
+            "ds_read_b32 %3, %8 offset:%10\n\t"
+            "ds_read_b32 %4, %8 offset:%11\n\t"
+            "ds_read_b32 %5, %8 offset:%12\n\t"
+            "ds_read_b32 %6, %8 offset:%13\n\t"
+            "ds_read_b32 %7, %8 offset:%14\n\t"
             "s_waitcnt lgkmcnt(0)"
-            : "=&v"(t0), "=&v"(t1), "=&v"(u0), "=&v"(u1), "=&v"(u2), "=&v"(u3), "=&v"(u4)
-            : "v"(addr));
+            : "=&v"(t0), "=&v"(u0), "=&v"(u1), "=&v"(u2), "=&v"(u3), "=&v"(u4), "=&v"(u5), "=&v"(u6)
+            : "v"(addr), "i"(4 * SY), "i"(4 * SY + 4), "i"(4 * SY + 8), "i"(8 * SY), "i"(8 * SY + 4),
+              "i"(8 * SY + 8));
         f[0][0] = t0.x; f[0][1] = t0.y; f[0][2] = u0;
-        f[1][0] = t1.x; f[1][1] = t1.y; f[1][2] = u1;
-        f[2][0] = u2; f[2][1] = u3; f[2][2] = u4;
+        f[1][0] = u1; f[1][1] = u2; f[1][2] = u3;
+        f[2][0] = u4; f[2][1] = u5; f[2][2] = u6;
     }
+}
+
+// Tensor Lagrange value of one cell from its K x K taps (clamped to the four
+// nearest nodes when CLAMP).
+template <int K, bool CLAMP>
+__device__ __forceinline__ float interp_taps(const float (&f)[K][K], const float (&lx)[K], const float (&ly)[K])
+{
+    constexpr int o0 = (K - 1) / 2;
+    float v;
+#pragma unroll
+    for (int a = 0; a < K; ++a) {
+        float r = ly[0] * f[a][0];
+#pragma unroll
+        for (int b = 1; b < K; ++b) r = fmaf(ly[b], f[a][b], r);
+        v = a == 0 ? lx[0] * r : fmaf(lx[a], r, v);
+    }
+    if constexpr (CLAMP) {
+        const float lo = fminf(fminf(f[o0][o0], f[o0][o0 + 1]), fminf(f[o0 + 1][o0], f[o0 + 1][o0 + 1]));
+        const float hi = fmaxf(fmaxf(f[o0][o0], f[o0][o0 + 1]), fmaxf(f[o0 + 1][o0], f[o0 + 1][o0 + 1]));
+        v = fminf(fmaxf(v, lo), hi);
+    }
+    return v;
 }
 
 // Kick and damping/diffusion of four consecutive rows j .. j+3 of one column.
@@ -293,21 +350,8 @@ __global__ __launch_bounds__(kThreads) void step32c_kernel(const SimDev *__restr
                         lagrange_fma<K>(__builtin_amdgcn_fractf(dx), lx);
                         lagrange_fma<K>(__builtin_amdgcn_fractf(dy), ly);
                         float f[K][K];
-                        read_taps<K>((unsigned)(__mul24(mx, 4 * SY) + cb4 + 4 * rb + 4 * my), f);
-                        float v;
-#pragma unroll
-                        for (int a = 0; a < K; ++a) {
-                            float r = ly[0] * f[a][0];
-#pragma unroll
-                            for (int b = 1; b < K; ++b) r = fmaf(ly[b], f[a][b], r);
-                            v = a == 0 ? lx[0] * r : fmaf(lx[a], r, v);
-                        }
-                        if constexpr (CLAMP) {
-                            const float lo = fminf(fminf(f[o0][o0], f[o0][o0 + 1]), fminf(f[o0 + 1][o0], f[o0 + 1][o0 + 1]));
-                            const float hi = fmaxf(fmaxf(f[o0][o0], f[o0][o0 + 1]), fmaxf(f[o0 + 1][o0], f[o0 + 1][o0 + 1]));
-                            v = fminf(fmaxf(v, lo), hi);
-                        }
-                        acol[rb] = v;
+                        read_taps<K, SY>((unsigned)(__mul24(mx, 4 * SY) + cb4 + 4 * rb + 4 * my), f);
+                        acol[rb] = interp_taps<K, CLAMP>(f, lx, ly);
                     }
                 }
             }

@@ -162,16 +162,17 @@ def test_haissinski_start_matches_oracle():
     assert np.abs(b.profile(0) - h0).max() < 0.1 * np.abs(b.profile(1) - g0).max()
 
 
+@pytest.mark.parametrize("K", [3, 4])
 @pytest.mark.parametrize("staged", [0, 1, 2, 3])
 @pytest.mark.parametrize("rotation", [0, 1])
 @pytest.mark.parametrize("clamp", [0, 1])
-def test_kernel_variants_match_oracle(staged, rotation, clamp):
+def test_kernel_variants_match_oracle(staged, rotation, clamp, K):
     """Every FP32 kernel layout (generic, staged 64-row chunks, staged 256-row
     chunks with the merged kick, staged 192-row chunks with 16-byte staging and
     per-row damping coefficients) and both rotations against the oracle."""
     sims = mixed_sims()
     for s in sims:
-        s.rotation, s.clamp = rotation, clamp
+        s.rotation, s.clamp, s.interp = rotation, clamp, K
     b = vfp.Batch([vfp.sim_kwargs(s, precision="fp32") for s in sims])
     b.set_tuning(0, True, staged)
     b.step(30)
