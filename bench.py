@@ -145,6 +145,8 @@ def main():
     ap.add_argument("--no-forms", action="store_true", help="skip the FP32 and Manhattan forms")
     ap.add_argument("--staged", type=int, default=None, help="FP32 step kernel layout: 0 generic, 1, 2, 3")
     ap.add_argument("--cells", type=int, default=0, help="cells per work unit (0: built-in)")
+    ap.add_argument("--streams", type=int, default=2, choices=[1, 2],
+                    help="stream groups of the batch (1: every launch covers the whole batch, as in profiles)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 512 MiB device copy 5 times (scale of the HBM byte counters)")
     ap.add_argument("--counter-summary", nargs=4, metavar=("FETCH", "WRITE", "COPY_FETCH", "COPY_WRITE"),
@@ -195,6 +197,7 @@ def main():
     if args.autotune:
         tuned, layout = b.autotune(ticks=10)
         log(f"autotuned: {tuned} cells per unit, kernel layout {layout}")
+    b.set_streams(args.streams)
     cells_unit, _, args.staged = b.get_tuning()
     b.step(args.warmup)
     torch.cuda.synchronize()
@@ -223,6 +226,7 @@ def main():
             fb = vfp.Batch([vfp.sim_kwargs(s_, precision=fprec, rotation=rot) for s_ in sims], stream=stream,
                            torch_workspace=True)
             fb.set_tuning(cells_unit, True, args.staged)
+            fb.set_streams(args.streams)
             fb.step(min(args.warmup, 20))
             fr = timed(fb, stream, cells_tick, 8 if fprec == "fp64" else 4, args.steps)
             forms[name] = {"value": fr["value"], "ms_per_step": fr["ms"] / args.steps,
@@ -285,7 +289,7 @@ def main():
                    "wake": {"fp16": "FP16 hi/lo MFMA", "bf16": "BF16 hi/lo MFMA",
                             "fp32": "FP32 VALU", "fp64": "FP64 VALU"}[prec],
                    "sims": len(sims), "cells_per_tick": cells_tick,
-                   "cells_per_unit": cells_unit, "kernel_layout": args.staged},
+                   "cells_per_unit": cells_unit, "kernel_layout": args.staged, "stream_groups": args.streams},
         "parity": None if err is None else {"max_rel_l1_vs_fp64_oracle": err, "after_steps": args.warmup,
                                             "sims_checked": "one per grid size"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
