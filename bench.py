@@ -220,7 +220,7 @@ def main():
     # the same workload in the other forms (same steps; no parity pass)
     forms = {}
     if not args.no_forms:
-        for name, fprec, rot in (("fp32_fused_wake", "fp32", 0), ("manhattan_" + prec, prec, 1)):
+        for name, fprec, rot in (("fp32", "fp32", 0), ("manhattan_" + prec, prec, 1)):
             if name.startswith("fp32") and prec == "fp32":
                 continue
             fb = vfp.Batch([vfp.sim_kwargs(s_, precision=fprec, rotation=rot) for s_ in sims], stream=stream,

@@ -331,7 +331,7 @@ int rebuild_units(vfp_batch *b)
     // matrix-core wake tiles
     b->wtiles.clear();
     b->lds_wake = 0;
-    if (b->precision >= VFP_MIXED_BF16) {
+    if (b->precision != VFP_FP64) {
       for (int g = 0; g < b->ngroups; ++g) {
         b->tile_off[g] = b->wtiles.size();
         for (int s : b->active) {
@@ -343,7 +343,10 @@ int rebuild_units(vfp_batch *b)
                 const int dmin = std::max(-(nb - 1), I0 - (nb - 1)), dmax = std::min(nb - 1, I0 + 15);
                 const size_t NR = 16 * (16 + dmax - dmin), NL = 16 * (dmax - dmin) + 31;
                 const size_t NLp = (NL + 1 + 7) & ~(size_t)7;
-                b->lds_wake = std::max(b->lds_wake, (2 * NR + 4 * NLp) * sizeof(uint16_t));
+                if (b->precision == VFP_FP32)
+                    b->lds_wake = std::max(b->lds_wake, (size_t)(2 * b->hs[s].p.n + 255) * sizeof(float));
+                else
+                    b->lds_wake = std::max(b->lds_wake, (2 * NR + 4 * NLp) * sizeof(uint16_t));
             }
         }
         b->tile_cnt[g] = b->wtiles.size() - b->tile_off[g];
@@ -442,7 +445,7 @@ int launch_tick_group(vfp_batch *b, int parity)
     if (b->cur_nunits == 0) return VFP_OK;
     const bool wake = any_wake(b);
     int t0 = -1, t1 = -1, t2 = -1;
-    const bool mfma = b->precision >= VFP_MIXED_BF16 && wake;
+    const bool mfma = b->precision != VFP_FP64 && wake;      // a separate wake kernel
     if (b->timing) {
         int rc = timing_event(b, &t0);
         if (rc) return rc;
@@ -450,9 +453,19 @@ int launch_tick_group(vfp_batch *b, int parity)
     if (b->precision == VFP_FP64) {
         if (wake) launch_step_k<double, WAKE_FUSED>(b, parity);
         else launch_step_k<double, WAKE_NONE>(b, parity);
-    } else if (b->precision == VFP_FP32 || !wake) {
-        if (wake) launch_step_k<float, WAKE_FUSED>(b, parity);
-        else launch_step_k<float, WAKE_NONE>(b, parity);
+    } else if (!wake) {
+        launch_step_k<float, WAKE_NONE>(b, parity);
+    } else if (b->precision == VFP_FP32) {
+        static int cur = 0;
+        lds_limit(wake_vec_kernel, b->lds_wake, cur);
+        if (b->cur_ntiles > 0)
+            hipLaunchKernelGGL(wake_vec_kernel, dim3((unsigned)b->cur_ntiles), dim3(kThreads), b->lds_wake,
+                               b->cur_stream, b->d_sd, b->cur_tiles, parity);
+        if (b->timing) {
+            int rc = timing_event(b, &t1);
+            if (rc) return rc;
+        }
+        launch_step_k<float, WAKE_EXTERNAL>(b, parity);
     } else {
         const bool fp16 = b->precision == VFP_MIXED_FP16;
         auto wk = fp16 ? wake_mfma2_kernel<true> : wake_mfma2_kernel<false>;

@@ -847,6 +847,61 @@ __global__ __launch_bounds__(kThreads) void wake_mfma2_kernel(const SimDev *__re
     VFP_WAKE_MARK(5);
 }
 
+// Vector-ALU wake of the FP32 form, one workgroup per (simulation, tile of
+// 256 rows): V_i = S s sum_j w[i-j] rho_j with FP32 products and partial sums
+// over blocks of 32 consecutive j, added in FP64 (Sec. II.B; the same term
+// definition as the fused wake of the FP64/generic kernel).  LDS: rho (n
+// floats) and the tile's lag window (n + 255 floats).
+__global__ __launch_bounds__(kThreads) void wake_vec_kernel(const SimDev *__restrict__ sims,
+                                                            const WakeTile *__restrict__ tiles, int parity)
+{
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    __shared__ double red[kWaves];
+    const WakeTile wt = tiles[blockIdx.x];
+    const SimDev &sd = sims[wt.sim];
+    const int n = sd.n, tid = threadIdx.x, lane = tid & 63;
+    const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int i0 = 256 * wt.tile;
+    float *rho = (float *)smem_raw;
+    float *lag = rho + n;                              // lag[k] = w[i0 + k - (n - 1)]
+    typedef const __attribute__((address_space(1))) double gdouble;
+    typedef const __attribute__((address_space(1))) float gfloat;
+    gdouble *cs = (gdouble *)sd.colsum[parity];
+    gfloat *wl = (gfloat *)sd.wl32;
+    double part = 0.0;
+#pragma unroll 4
+    for (int k = tid; k < n; k += kThreads) {
+        const double v = cs[k];
+        part += v;
+        rho[k] = (float)(sd.dp * v);
+    }
+#pragma unroll 4
+    for (int k = tid; k < n + 255; k += kThreads) {
+        const int ix = i0 + k;                         // wl32 index = lag + n - 1
+        lag[k] = ix <= 2 * n - 2 ? wl[ix] : 0.0f;
+    }
+    part = wave_sum(part);
+    if (lane == 0) red[wv] = part;
+    __syncthreads();
+    part = red[0];
+    for (int k = 1; k < kWaves; ++k) part += red[k];
+    const double s = sd.renorm ? sd.Q0 / (part * sd.dq * sd.dp) : 1.0;
+    const int i = i0 + tid;
+    if (i < n) {
+        const float *lw = lag + tid + n - 1;           // lw[-j] = w[i - j]
+        double acc = 0.0;
+        for (int jb = 0; jb < n; jb += 32) {
+            float a32 = 0.0f;
+            const int je = jb + 32 < n ? jb + 32 : n;
+#pragma unroll 8
+            for (int j = jb; j < je; ++j) a32 = fmaf(lw[-j], rho[j], a32);
+            acc += a32;
+        }
+        sd.vext[i] = (float)(sd.S * s * acc);
+    }
+    if (wt.tile == 0 && tid == 0) sd.sext[0] = s;
+}
+
 // CSR spectrum of the state whose profile the diagnostics kernel left in
 // rho_out (Sec. IV.C): out[k] = (S/M) m_k Re Z_k |rho~_k|^2, k = 0..M/2,
 // rho~_k the DFT of the zero-padded profile, m_k = 2 for the bins that stand
