@@ -95,15 +95,44 @@ typedef struct vfp_params {
     const double *psi0;       /* n*n initial density; NULL: unit Gaussian          */
     int64_t max_steps;        /* batch only: the simulation stops advancing after
                                  this many steps (0: never)                        */
+    int32_t z_model;          /* VFP_Z_*: where Z_k comes from.  VFP_Z_SAMPLES:
+                                 the z_re/z_im arrays above; otherwise Z_k is
+                                 computed on the device at the same kappa_k and
+                                 z_re/z_im must be NULL (Sec. II.B models).      */
+    double  z_shield;         /* VFP_Z_PARALLEL_PLATES: shielding parameter
+                                 Pi > 0 (P = Pi^(2/3)); ignored otherwise         */
 } vfp_params;
+
+/* Impedance models of Sec. II.B in normalised form (kappa = k sigma_z0, all
+ * physical prefactors in z_scale):
+ *   free space:       Z = Gamma(2/3) 3^(-1/3) kappa^(1/3) (sqrt(3)/2 + i/2)
+ *   parallel plates:  Z = 4 pi^2 2^(1/3) P kappa^(-1/3)
+ *                         sum_{p>=0} [Ai'(u_p) Ci'(u_p) + u_p Ai(u_p) Ci(u_p)],
+ *                     Ci = Ai - i Bi, u_p = pi^2 (2p+1)^2 2^(-2/3) P^2 kappa^(-4/3)
+ * Z_0 = 0 in both (the mean of the wake is not a force). */
+enum {
+    VFP_Z_SAMPLES = 0,          /* caller-supplied samples z_re/z_im (or none)      */
+    VFP_Z_PARALLEL_PLATES = 1,  /* shielded CSR, Pi = z_shield                       */
+    VFP_Z_FREE_SPACE = 2        /* unshielded CSR                                    */
+};
 
 typedef struct vfp_batch vfp_batch;   /* a set of independent simulations      */
 typedef struct vfp_batch vfp_sim;     /* a single simulation: a set of one     */
 
 /* Defaults: n = 256, [-8, 8]^2, 1000 steps per period, beta = 1e-3, K = 4,
  * no clamp, renormalize = 1, VFP_FP32, padding = 2, standard rotation,
- * zero current, Gaussian start, max_steps = 0. */
+ * zero current, Gaussian start, max_steps = 0, VFP_Z_SAMPLES, z_shield = 1. */
 void vfp_params_init(vfp_params *p);
+
+/* The impedance samples a simulation with z_model = `model` uses: Z_k at
+ * kappa_k = 2*pi*k/(M*dq), k = 0..M/2, M = padding*n, dq = (q_max-q_min)/(n-1)
+ * (Sec. II.B; the sampling of the wake's discrete convolution, Sec. III.C),
+ * computed in FP64 on the current device with the same code the create calls
+ * use.  z_re/z_im are HOST arrays of M/2+1 doubles owned by the caller.
+ * model: VFP_Z_PARALLEL_PLATES (Pi > 0) or VFP_Z_FREE_SPACE.  Synchronous.
+ * Returns VFP_EINVAL for bad arguments, VFP_EDEVICE on a HIP failure. */
+int vfp_impedance_samples(int32_t model, int32_t n, int32_t padding, double q_min, double q_max,
+                          double Pi, double *z_re, double *z_im);
 
 /* sizeof(vfp_params) as compiled into the library (binding layout check). */
 size_t vfp_params_sizeof(void);

@@ -22,6 +22,7 @@
 #include "vfp_step32.hpp"
 #include "vfp_step32b.hpp"
 #include "vfp_step32c.hpp"
+#include "vfp_impedance.hpp"
 
 using namespace vfp;
 
@@ -82,10 +83,10 @@ int choose_strip(int n, int cells)
 // chunk keeps every staged column of a wave in the prefetch registers.
 // The dynamic LDS of a unit stays under kLdsBudgetC so that five workgroups
 // fit on a compute unit.
-#ifndef VFP_LDS_BUDGET_KB
-#define VFP_LDS_BUDGET_KB 28
+#ifndef VFP_LDS_BUDGET
+#define VFP_LDS_BUDGET (28 * 1024)
 #endif
-constexpr size_t kLdsBudgetC = VFP_LDS_BUDGET_KB * 1024;
+constexpr size_t kLdsBudgetC = VFP_LDS_BUDGET;
 size_t lds_bytes_c(int n, int w, int rotation)
 {
     return ((size_t)w * (n + 2 * kPad) + (size_t)(w + 2 * kH) * kSYC + (rotation ? (size_t)w * kSYC : 0)) * 4;
@@ -118,6 +119,12 @@ int validate(const vfp_params &p, std::string &why)
     if (p.padding < 2 || (int64_t)p.padding * p.n > (1 << 24)) { why = "padding must be >= 2"; return VFP_EINVAL; }
     if (p.rotation != VFP_ROT_STANDARD && p.rotation != VFP_ROT_MANHATTAN) { why = "unknown rotation"; return VFP_EINVAL; }
     if ((p.z_re == nullptr) != (p.z_im == nullptr)) { why = "z_re and z_im must both be set or both NULL"; return VFP_EINVAL; }
+    if (p.z_model < VFP_Z_SAMPLES || p.z_model > VFP_Z_FREE_SPACE) { why = "unknown z_model"; return VFP_EINVAL; }
+    if (p.z_model != VFP_Z_SAMPLES && p.z_re) { why = "z_re/z_im must be NULL when z_model computes Z"; return VFP_EINVAL; }
+    if (p.z_model == VFP_Z_PARALLEL_PLATES && !(p.z_shield > 0.0 && std::isfinite(p.z_shield))) {
+        why = "z_shield must be finite and > 0";
+        return VFP_EINVAL;
+    }
     if (!std::isfinite(p.z_scale)) { why = "z_scale must be finite"; return VFP_EINVAL; }
     if (p.max_steps < 0) { why = "max_steps must be >= 0"; return VFP_EINVAL; }
     const double dp = (p.p_max - p.p_min) / (p.n - 1);
@@ -867,7 +874,7 @@ int create_impl(const vfp_params *p, int32_t count, void *stream, void *ws, size
         d.rotation = q.rotation;
         d.clamp = q.clamp;
         d.renorm = q.renormalize;
-        d.has_wake = p[s].z_re != nullptr ? 1 : 0;
+        d.has_wake = (p[s].z_re != nullptr || p[s].z_model != VFP_Z_SAMPLES) ? 1 : 0;
         d.M = q.padding * q.n;
         d.q_min = q.q_min;
         d.p_min = q.p_min;
@@ -951,11 +958,23 @@ int create_impl(const vfp_params *p, int32_t count, void *stream, void *ws, size
         const int n = h.p.n, M = b->sd[s].M, nz = M / 2 + 1;
         rc = ensure_stage(b, 2 * (size_t)nz);
         if (rc) return bail(rc);
-        if (upload(b->d_stage, h.zr.data(), nz * sizeof(double), b->stream) ||
-            upload(b->d_stage + nz, h.zi.data(), nz * sizeof(double), b->stream))
-            return bail(fail(VFP_EDEVICE, "impedance upload failed"));
-        if (upload(b->arena + h.off_zr, h.zr.data(), nz * sizeof(double), b->stream))
-            return bail(fail(VFP_EDEVICE, "impedance upload failed"));
+        if (h.p.z_model != VFP_Z_SAMPLES) {
+            // Z_k computed on the device at kappa_k = 2 pi k / (M dq)
+            const double dq = (h.p.q_max - h.p.q_min) / (n - 1);
+            hipLaunchKernelGGL(impedance_kernel, dim3((nz + kThreads - 1) / kThreads), dim3(kThreads), 0, b->stream,
+                               nz, 2.0 * M_PI / (M * dq), h.p.z_model, std::pow(h.p.z_shield, 2.0 / 3.0),
+                               b->d_stage, b->d_stage + nz);
+            if (hipGetLastError() != hipSuccess ||
+                hipMemcpyAsync(b->arena + h.off_zr, b->d_stage, nz * sizeof(double), hipMemcpyDeviceToDevice,
+                               b->stream) != hipSuccess)
+                return bail(fail(VFP_EDEVICE, "impedance evaluation failed"));
+        } else {
+            if (upload(b->d_stage, h.zr.data(), nz * sizeof(double), b->stream) ||
+                upload(b->d_stage + nz, h.zi.data(), nz * sizeof(double), b->stream))
+                return bail(fail(VFP_EDEVICE, "impedance upload failed"));
+            if (upload(b->arena + h.off_zr, h.zr.data(), nz * sizeof(double), b->stream))
+                return bail(fail(VFP_EDEVICE, "impedance upload failed"));
+        }
         hipLaunchKernelGGL(wake_table_kernel, dim3((2 * n - 1 + kThreads - 1) / kThreads), dim3(kThreads), 0,
                            b->stream, n, M, b->d_stage, b->d_stage + nz, (double *)(b->arena + h.off_wl64),
                            (float *)(b->arena + h.off_wl32));
@@ -1094,9 +1113,35 @@ void vfp_params_init(vfp_params *p)
     p->rotation = VFP_ROT_STANDARD;
     p->z_scale = 0.0;
     p->max_steps = 0;
+    p->z_model = VFP_Z_SAMPLES;
+    p->z_shield = 1.0;
 }
 
 size_t vfp_params_sizeof(void) { return sizeof(vfp_params); }
+
+int vfp_impedance_samples(int32_t model, int32_t n, int32_t padding, double q_min, double q_max, double Pi,
+                          double *z_re, double *z_im)
+{
+    if (model != VFP_Z_PARALLEL_PLATES && model != VFP_Z_FREE_SPACE) return fail(VFP_EINVAL, "unknown impedance model");
+    if (n < 16 || n > 4096 || padding < 2 || (int64_t)padding * n > (1 << 24))
+        return fail(VFP_EINVAL, "need n in [16, 4096] and padding >= 2");
+    if (!(q_max > q_min) || !std::isfinite(q_min) || !std::isfinite(q_max))
+        return fail(VFP_EINVAL, "need finite q_min < q_max");
+    if (model == VFP_Z_PARALLEL_PLATES && !(Pi > 0.0 && std::isfinite(Pi)))
+        return fail(VFP_EINVAL, "Pi must be finite and > 0");
+    if (!z_re || !z_im) return fail(VFP_EINVAL, "z_re and z_im are required");
+    const int M = padding * n, nz = M / 2 + 1;
+    const double dq = (q_max - q_min) / (n - 1);
+    double *d = nullptr;
+    HIPCHK(hipMalloc(&d, 2 * (size_t)nz * sizeof(double)));
+    hipLaunchKernelGGL(impedance_kernel, dim3((nz + kThreads - 1) / kThreads), dim3(kThreads), 0, nullptr, nz,
+                       2.0 * M_PI / (M * dq), model, std::pow(Pi, 2.0 / 3.0), d, d + nz);
+    const bool ok = hipGetLastError() == hipSuccess &&
+                    hipMemcpy(z_re, d, nz * sizeof(double), hipMemcpyDeviceToHost) == hipSuccess &&
+                    hipMemcpy(z_im, d + nz, nz * sizeof(double), hipMemcpyDeviceToHost) == hipSuccess;
+    (void)hipFree(d);
+    return ok ? VFP_OK : fail(VFP_EDEVICE, "impedance evaluation failed");
+}
 
 const char *vfp_last_error(void) { return g_err.c_str(); }
 

@@ -19,6 +19,8 @@ LIB_PATH = os.path.join(HERE, "libvfp.so")
 VFP_OK, VFP_EINVAL, VFP_ENOMEM, VFP_EDEVICE, VFP_ESTATE, VFP_EUNSTABLE = 0, -1, -2, -3, -4, -5
 FP64, FP32, MIXED_BF16, MIXED_FP16 = 0, 1, 2, 3
 ROT_STANDARD, ROT_MANHATTAN = 0, 1
+Z_SAMPLES, Z_PARALLEL_PLATES, Z_FREE_SPACE = 0, 1, 2
+Z_MODELS = {"samples": Z_SAMPLES, "parallel_plate": Z_PARALLEL_PLATES, "free_space": Z_FREE_SPACE}
 PRECISIONS = {"fp64": FP64, "fp32": FP32, "bf16": MIXED_BF16, "fp16": MIXED_FP16}
 
 _dp = C.POINTER(C.c_double)
@@ -31,7 +33,7 @@ class Params(C.Structure):
         ("beta", C.c_double), ("interp", C.c_int32), ("clamp", C.c_int32),
         ("renormalize", C.c_int32), ("precision", C.c_int32), ("padding", C.c_int32),
         ("rotation", C.c_int32), ("z_re", _dp), ("z_im", _dp), ("z_scale", C.c_double),
-        ("psi0", _dp), ("max_steps", C.c_int64),
+        ("psi0", _dp), ("max_steps", C.c_int64), ("z_model", C.c_int32), ("z_shield", C.c_double),
     ]
 
 
@@ -69,6 +71,8 @@ def load():
         sig = {
             "vfp_params_init": (None, [P]),
             "vfp_params_sizeof": (C.c_size_t, []),
+            "vfp_impedance_samples": (C.c_int, [C.c_int32, C.c_int32, C.c_int32, C.c_double, C.c_double,
+                                                C.c_double, _dp, _dp]),
             "vfp_workspace_size": (C.c_int, [P, C.c_int32, C.POINTER(C.c_size_t)]),
             "vfp_create": (C.c_int, [P, h, h, C.c_size_t, C.POINTER(h)]),
             "vfp_step": (C.c_int, [h, C.c_int64]),
@@ -138,7 +142,7 @@ def _ptr(a):
 def make_params(n=256, q_range=(-8.0, 8.0), p_range=None, steps_per_period=1000, beta=1e-3,
                 interp=4, clamp=0, renormalize=1, precision="fp32", padding=2,
                 rotation=ROT_STANDARD, z_re=None, z_im=None, z_scale=0.0, psi0=None,
-                max_steps=0):
+                max_steps=0, z_model="samples", z_shield=1.0):
     """Returns (Params, keepalive) -- keepalive holds the numpy arrays the
     struct points to until the create call has copied them."""
     p = Params()
@@ -163,7 +167,22 @@ def make_params(n=256, q_range=(-8.0, 8.0), p_range=None, steps_per_period=1000,
     ps = _f64(psi0, None if psi0 is None else p.n * p.n)
     p.psi0 = _ptr(ps)
     p.max_steps = int(max_steps)
+    p.z_model = Z_MODELS[z_model] if isinstance(z_model, str) else int(z_model)
+    p.z_shield = float(z_shield)
     return p, (zr, zi, ps)
+
+
+def impedance_samples(n, padding, q_min, q_max, model="parallel_plate", Pi=1.0):
+    """Z_k at kappa_k = 2 pi k / (M dq), k = 0..M/2, evaluated on the device
+    (the samples a simulation created with z_model=model uses).  Returns
+    (z_re, z_im) as float64 arrays."""
+    M = int(padding) * int(n)
+    zr = np.empty(M // 2 + 1, dtype=np.float64)
+    zi = np.empty(M // 2 + 1, dtype=np.float64)
+    m = Z_MODELS[model] if isinstance(model, str) else int(model)
+    _check(load().vfp_impedance_samples(m, int(n), int(padding), float(q_min), float(q_max), float(Pi),
+                                        _ptr(zr), _ptr(zi)))
+    return zr, zi
 
 
 def _stream_handle(stream):
@@ -412,13 +431,19 @@ class Sim:
             pass
 
 
-def sim_kwargs(sim, precision="fp32", **over) -> dict:
-    """Keyword arguments for Sim/Batch from an ``inputs.Sim`` recipe."""
-    zr, zi = sim.impedance()
+def sim_kwargs(sim, precision="fp32", device_impedance=False, **over) -> dict:
+    """Keyword arguments for Sim/Batch from an ``inputs.Sim`` recipe.  With
+    device_impedance the impedance of the recipe's model is evaluated by the
+    library on the device instead of being passed as host samples."""
+    has_z = sim.Pi is not None and sim.z_scale != 0.0
     d = dict(n=sim.n, q_range=(sim.q_min, sim.q_max), p_range=(sim.p_min, sim.p_max),
              steps_per_period=sim.steps_per_period, beta=sim.beta, interp=sim.interp,
              clamp=sim.clamp, renormalize=sim.renormalize, precision=precision,
-             padding=sim.padding, rotation=sim.rotation, z_re=zr, z_im=zi,
-             z_scale=sim.z_scale if zr is not None else 0.0, psi0=sim.psi0())
+             padding=sim.padding, rotation=sim.rotation,
+             z_scale=sim.z_scale if has_z else 0.0, psi0=sim.psi0())
+    if has_z and device_impedance:
+        d.update(z_model=sim.model, z_shield=sim.Pi)
+    else:
+        d["z_re"], d["z_im"] = sim.impedance()
     d.update(over)
     return d

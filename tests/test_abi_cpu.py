@@ -40,6 +40,24 @@ def test_params_defaults():
     vfp.load().vfp_params_init(C.byref(p))
     assert (p.n, p.steps_per_period, p.interp, p.precision, p.padding, p.renormalize) == (256, 1000, 4, 1, 2, 1)
     assert p.q_min == -8.0 and p.p_max == 8.0 and p.beta == 1e-3 and not p.z_re
+    assert p.z_model == vfp.Z_SAMPLES and p.z_shield == 1.0
+
+
+def test_device_impedance_models_validate_on_the_host():
+    assert _ws(z_model="free_space", z_scale=1.0)[0] == 0
+    assert _ws(z_model="parallel_plate", z_shield=0.4, z_scale=1.0)[0] == 0
+
+
+@pytest.mark.parametrize("args,msg", [
+    ((0, 64, 2, -8.0, 8.0, 1.0), "model"),
+    ((1, 8, 2, -8.0, 8.0, 1.0), "n in"),
+    ((1, 64, 1, -8.0, 8.0, 1.0), "padding"),
+    ((1, 64, 2, 8.0, -8.0, 1.0), "q_min"),
+    ((1, 64, 2, -8.0, 8.0, -1.0), "Pi"),
+])
+def test_impedance_samples_rejects_bad_arguments_on_the_host(args, msg):
+    with pytest.raises(vfp.VfpError, match=msg):
+        vfp.impedance_samples(*args[1:3], *args[3:5], model=args[0], Pi=args[5])
 
 
 def _ws(**kw):
@@ -66,6 +84,10 @@ def test_workspace_size_scales_with_grid_and_precision():
     (dict(q_range=(1.0, -1.0)), vfp.VFP_EINVAL, "q_min"),
     (dict(precision=9), vfp.VFP_EINVAL, "precision"),
     (dict(beta=50.0, steps_per_period=10), vfp.VFP_EUNSTABLE, "unstable"),
+    (dict(z_model=3), vfp.VFP_EINVAL, "z_model"),
+    (dict(z_model="parallel_plate", z_shield=0.0), vfp.VFP_EINVAL, "z_shield"),
+    (dict(z_model="parallel_plate", z_shield=float("inf")), vfp.VFP_EINVAL, "z_shield"),
+    (dict(z_model="free_space", z_re=np.zeros(257), z_im=np.zeros(257)), vfp.VFP_EINVAL, "NULL"),
 ])
 def test_validation_errors(kw, code, msg):
     rc, _, err = _ws(**kw)
