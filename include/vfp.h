@@ -92,7 +92,10 @@ typedef struct vfp_params {
     const double *z_im;       /* kappa_k = 2*pi*k/(M*dq); both NULL: zero current.  */
                               /* Im Z_0 and Im Z_{M/2} are ignored (Hermitian).     */
     double  z_scale;          /* S in V = S * (w conv rho) (normalised current)    */
-    const double *psi0;       /* n*n initial density; NULL: unit Gaussian          */
+    const double *psi0;       /* n*n initial density, index i*n+j (p fastest);
+                                 NULL: unit Gaussian.  Finite, within the binary32
+                                 range unless VFP_FP64, and with a positive,
+                                 finite sum (Q0 > 0), else VFP_EINVAL.            */
     int64_t max_steps;        /* batch only: the simulation stops advancing after
                                  this many steps (0: never)                        */
     int32_t z_model;          /* VFP_Z_*: where Z_k comes from.  VFP_Z_SAMPLES:
@@ -166,7 +169,8 @@ int vfp_csr_power(vfp_sim *sim, double *power);
 int vfp_moments(vfp_sim *sim, double out[5]);
 
 /* Copy the current state out (n*n FP64) / replace it (resets Q0 to the
- * charge of the new psi and the step counter to 0). */
+ * charge of the new psi and the step counter to 0; psi is checked as psi0
+ * is, VFP_EINVAL otherwise). */
 int vfp_get_psi(vfp_sim *sim, double *psi);
 int vfp_set_psi(vfp_sim *sim, const double *psi);
 

@@ -11,6 +11,7 @@
 
 #include <algorithm>
 #include <chrono>
+#include <cfloat>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -102,6 +103,21 @@ int choose_strip_c(int n, int cells, int rotation)
 }
 
 
+// a density must be finite and, in the FP32-storage forms, representable in
+// binary32, with a positive, finite charge (the moments are charge-weighted)
+const char *density_error(const double *psi, size_t nn, int precision)
+{
+    const double lim = precision == VFP_FP64 ? DBL_MAX : (double)FLT_MAX;
+    double sum = 0.0;
+    for (size_t z = 0; z < nn; ++z) {
+        if (!(std::fabs(psi[z]) <= lim))
+            return precision == VFP_FP64 ? "psi must be finite" : "psi must be finite and within the binary32 range";
+        sum += psi[z];
+    }
+    if (!(sum > 0.0) || !std::isfinite(sum)) return "psi must have a positive, finite charge";
+    return nullptr;
+}
+
 int validate(const vfp_params &p, std::string &why)
 {
     if (p.n < 16 || p.n > 4096) { why = "n must be in [16, 4096]"; return VFP_EINVAL; }
@@ -142,9 +158,10 @@ int validate(const vfp_params &p, std::string &why)
             }
     }
     if (p.psi0) {
-        const size_t nn = (size_t)p.n * p.n;
-        for (size_t z = 0; z < nn; ++z)
-            if (!std::isfinite(p.psi0[z])) { why = "psi0 must be finite"; return VFP_EINVAL; }
+        if (const char *e = density_error(p.psi0, (size_t)p.n * p.n, p.precision)) {
+            why = std::string("psi0: ") + e;
+            return VFP_EINVAL;
+        }
     }
     return VFP_OK;
 }
@@ -1233,8 +1250,7 @@ int vfp_batch_set_psi(vfp_batch *b, int32_t i, const double *psi)
 {
     if (!b || !psi || i < 0 || i >= b->count) return fail(VFP_EINVAL, "invalid arguments");
     const size_t nn = (size_t)b->hs[i].p.n * b->hs[i].p.n;
-    for (size_t z = 0; z < nn; ++z)
-        if (!std::isfinite(psi[z])) return fail(VFP_EINVAL, "psi must be finite");
+    if (const char *e = density_error(psi, nn, b->precision)) return fail(VFP_EINVAL, e);
     HIPCHK(hipStreamSynchronize(b->stream));
     const int rc = upload_psi(b, i, psi, false);
     if (rc) return rc;

@@ -43,6 +43,11 @@ def test_params_defaults():
     assert p.z_model == vfp.Z_SAMPLES and p.z_shield == 1.0
 
 
+def test_densities_the_storage_holds_are_accepted():
+    assert _ws(n=16, psi0=np.full(256, 1e39), precision="fp64")[0] == 0
+    assert _ws(n=16, psi0=np.full(256, 3e38), precision="fp32")[0] == 0
+
+
 def test_device_impedance_models_validate_on_the_host():
     assert _ws(z_model="free_space", z_scale=1.0)[0] == 0
     assert _ws(z_model="parallel_plate", z_shield=0.4, z_scale=1.0)[0] == 0
@@ -84,6 +89,12 @@ def test_workspace_size_scales_with_grid_and_precision():
     (dict(q_range=(1.0, -1.0)), vfp.VFP_EINVAL, "q_min"),
     (dict(precision=9), vfp.VFP_EINVAL, "precision"),
     (dict(beta=50.0, steps_per_period=10), vfp.VFP_EUNSTABLE, "unstable"),
+    (dict(n=16, psi0=np.full(256, 1e39)), vfp.VFP_EINVAL, "binary32"),
+    (dict(n=16, psi0=np.full(256, 1e39), precision="fp16"), vfp.VFP_EINVAL, "binary32"),
+    (dict(n=16, psi0=np.zeros(256)), vfp.VFP_EINVAL, "positive, finite charge"),
+    (dict(n=16, psi0=np.zeros(256), renormalize=0), vfp.VFP_EINVAL, "positive, finite charge"),
+    (dict(n=16, psi0=-np.ones(256), precision="fp64"), vfp.VFP_EINVAL, "positive, finite charge"),
+    (dict(n=16, psi0=np.full(256, 1e307), precision="fp64"), vfp.VFP_EINVAL, "positive, finite charge"),
     (dict(z_model=3), vfp.VFP_EINVAL, "z_model"),
     (dict(z_model="parallel_plate", z_shield=0.0), vfp.VFP_EINVAL, "z_shield"),
     (dict(z_model="parallel_plate", z_shield=float("inf")), vfp.VFP_EINVAL, "z_shield"),
