@@ -102,6 +102,13 @@ def load():
         lib.vfo_run.restype = C.c_long
         lib.vfo_run_many.argtypes = [C.c_int, P, C.POINTER(_dp), C.POINTER(_dp),
                                      C.POINTER(C.c_long), _dp]
+        _ip = C.POINTER(C.c_longlong)
+        lib.vfo_fix_quantize.argtypes = [C.c_int, _dp, _ip, C.c_long]
+        lib.vfo_fix_charge.argtypes = [P, C.c_int, _ip]
+        lib.vfo_fix_charge.restype = C.c_double
+        lib.vfo_fix_step.argtypes = [P, C.c_int, _dp, _ip, C.c_double, _dp, _ip, _dp]
+        lib.vfo_fix_run.argtypes = [P, C.c_int, _dp, _ip, C.c_long, C.c_double, _dp]
+        lib.vfo_fix_run.restype = C.c_int
         _lib = lib
     return _lib
 
@@ -245,3 +252,49 @@ def run_many(params, ws, psis, nsteps, Q0s):
     q0 = _a(Q0s, count)
     load().vfo_run_many(count, arr, wptrs, pptrs, steps, _ptr(q0))
     return [x.reshape(q.n, q.n) for x, q in zip(ps, params)]
+
+
+# ---------------------------------------------------------------- fixed point
+def _i64(x, n=None):
+    x = np.ascontiguousarray(x, dtype=np.int64)
+    if n is not None and x.size != n:
+        raise ValueError(f"expected {n} values, got {x.size}")
+    return x
+
+
+def _iptr(x):
+    return x.ctypes.data_as(C.POINTER(C.c_longlong))
+
+
+def fix_quantize(F: int, x) -> np.ndarray:
+    """raw = round(x * 2^F), ties to even."""
+    x = _a(x)
+    raw = np.zeros(x.shape, dtype=np.int64)
+    load().vfo_fix_quantize(int(F), _ptr(x), _iptr(raw), x.size)
+    return raw
+
+
+def fix_charge(p: OracleParams, F: int, raw) -> float:
+    return load().vfo_fix_charge(C.byref(p.c()), int(F), _iptr(_i64(raw, p.n * p.n)))
+
+
+def fix_step(p: OracleParams, F: int, w, raw, Q0: float):
+    """One fixed-point step.  Returns (raw_next, s used by the step)."""
+    out = _i64(raw, p.n * p.n).copy()
+    work = np.zeros(2 * p.n * p.n, dtype=np.int64)
+    dwork = np.zeros(4 * p.n)
+    s = C.c_double()
+    wp = None if w is None else _a(w, p.padding * p.n)
+    load().vfo_fix_step(C.byref(p.c()), int(F), _ptr(wp), _iptr(out), float(Q0), C.byref(s), _iptr(work),
+                        _ptr(dwork))
+    return out.reshape(p.n, p.n), s.value
+
+
+def fix_run(p: OracleParams, F: int, w, raw, nsteps: int, Q0: float):
+    """Returns (raw_final, s_final); the physical density is s_final * raw * 2^-F."""
+    out = _i64(raw, p.n * p.n).copy()
+    s = C.c_double()
+    wp = None if w is None else _a(w, p.padding * p.n)
+    if load().vfo_fix_run(C.byref(p.c()), int(F), _ptr(wp), _iptr(out), int(nsteps), float(Q0), C.byref(s)):
+        raise MemoryError("oracle run failed to allocate")
+    return out.reshape(p.n, p.n), s.value

@@ -506,3 +506,260 @@ void vfo_run_many(int count, const vfo_params *ps, const double *const *ws, doub
     for (int s = 0; s < count; ++s)
         vfo_run(&ps[s], ws[s], psis[s], nsteps[s], Q0s[s], 0, NULL, 0);
 }
+
+/* ================================================================== */
+/* Fixed-point density (Sec. III.A, last paragraph: psi held in memory */
+/* as a fixed-point number whose count F of fractional bits is chosen   */
+/* freely; Sec. IV.A and the table of converged bunch lengths compare   */
+/* F = 34 .. 59 with binary32 and binary64).  A stored value is a       */
+/* two's-complement integer raw with value raw * 2^-F.                  */
+/*                                                                      */
+/* The paper does not say how the arithmetic around the stored values   */
+/* is done; the reading taken here:                                     */
+/*  - every coefficient (interpolation weights, Fokker-Planck stencil   */
+/*    coefficients, renormalisation factor) is evaluated in FP64 exactly */
+/*    as in the FP64 form above, then rounded to the nearest F-bit       */
+/*    fixed-point value (ties to even);                                  */
+/*  - each weighted sum is accumulated exactly in 128-bit integers and   */
+/*    rounded once to F bits, half up: (acc + 2^(F-1)) >> F;             */
+/*  - the 2-D rotation sums each stencil row along p, rounds, then sums  */
+/*    the rows along q and rounds (the tensor product taken row first);  */
+/*  - the charge is an exact integer sum, converted as                   */
+/*    (double)H * 2^32 + (double)L, where H and L sum the arithmetic     */
+/*    high halves (raw >> 32) and the low halves (raw & (2^32-1));       */
+/*  - the stored density is not rescaled in place: the factor            */
+/*    s_t = Q0 / Q(psi_t) multiplies the rotated values of step t, so    */
+/*    the state after a step is s_{t+1} * psi_{t+1};                     */
+/*  - the wake stays FP64 (the paper computes it for floating-point      */
+/*    types only), from rho_i = s_t * dp * colsum_i;                     */
+/*  - the kick shift V_i*dtheta/dp is split once per column into its     */
+/*    floor and fraction, so every row of a column uses the same weights.*/
+/* F must lie in [16, 59] and |psi| stay below 2^(61-F).                */
+/* ================================================================== */
+typedef long long fx_t;
+typedef __int128 fx2_t;
+
+/* round a FP64 coefficient to F fractional bits */
+static fx_t fx_coef(double x, int F) { return llrint(ldexp(x, F)); }
+
+/* round an exact sum of F+F fractional bits to F bits, half up */
+static fx_t fx_round(fx2_t acc, int F) { return (fx_t)((acc + ((fx2_t)1 << (F - 1))) >> F); }
+
+static fx_t fx_node(const fx_t *psi, int n, int i, int j)
+{
+    if (i < 0 || i >= n || j < 0 || j >= n) return 0;
+    return psi[(size_t)i * n + j];
+}
+
+/* high/low half sums of one column, exact */
+static void fx_column_parts(const fx_t *col, int n, long long *h, long long *l)
+{
+    long long a = 0, b = 0;
+    for (int j = 0; j < n; ++j) {
+        a += col[j] >> 32;
+        b += col[j] & 0xffffffffLL;
+    }
+    *h = a;
+    *l = b;
+}
+
+static double fx_parts_value(long long h, long long l) { return (double)h * 4294967296.0 + (double)l; }
+
+void vfo_fix_quantize(int F, const double *x, fx_t *raw, long count)
+{
+    for (long z = 0; z < count; ++z) raw[z] = fx_coef(x[z], F);
+}
+
+/* charge dq*dp*sum(psi) of a fixed-point density, from the exact sum */
+double vfo_fix_charge(const vfo_params *p, int F, const fx_t *psi)
+{
+    const int n = p->n;
+    long long H = 0, L = 0;
+    for (int i = 0; i < n; ++i) {
+        long long h, l;
+        fx_column_parts(psi + (size_t)i * n, n, &h, &l);
+        H += h;
+        L += l;
+    }
+    return ldexp(fx_parts_value(H, L), -F) * grid_dq(p) * grid_dp(p);
+}
+
+/* 1-D fixed-point interpolation with weights W at integer base m, along
+ * p (column i) or along q (row j); clamp to the two bracketing nodes */
+static fx2_t fx_interp(const fx_t *psi, int n, int K, int along_p, int fixed, int m, const fx_t *W)
+{
+    fx2_t acc = 0;
+    for (int k = 0; k < K; ++k) {
+        const int x = m + stencil_offset(K, k);
+        const fx_t f = along_p ? fx_node(psi, n, fixed, x) : fx_node(psi, n, x, fixed);
+        acc += (fx2_t)W[k] * f;
+    }
+    return acc;   /* exact, 2F fractional bits; rounded by the caller */
+}
+
+static fx_t fx_clip(fx_t v, fx_t a, fx_t b)
+{
+    const fx_t lo = a < b ? a : b, hi = a < b ? b : a;
+    return v < lo ? lo : (v > hi ? hi : v);
+}
+
+static void fx_weights(int K, double t, int F, fx_t *W)
+{
+    double l[4];
+    vfo_lagrange_weights(K, t, l);
+    for (int k = 0; k < K; ++k) W[k] = fx_coef(l[k], F);
+}
+
+/* One time step of the fixed-point density (same sub-steps and order as
+ * vfo_step).  psi holds the stored density psi_t and is replaced by
+ * psi_{t+1}; *s_used receives s_t.  work: 2*n*n fixed values and 4*n
+ * doubles.  w may be NULL (zero current). */
+void vfo_fix_step(const vfo_params *p, int F, const double *w, fx_t *psi, double Q0, double *s_used,
+                  fx_t *work, double *dwork)
+{
+    const int n = p->n, K = p->interp;
+    const size_t nn = (size_t)n * n;
+    const double dq = grid_dq(p), dp = grid_dp(p), th = step_angle(p);
+    fx_t *a = work, *b = work + nn;
+    double *cd = dwork, *rho = dwork + n, *V = dwork + 2 * n;
+    /* renormalisation factor from the exact charge */
+    long long H = 0, L = 0;
+    for (int i = 0; i < n; ++i) {
+        long long h, l;
+        fx_column_parts(psi + (size_t)i * n, n, &h, &l);
+        H += h;
+        L += l;
+        cd[i] = fx_parts_value(h, l);
+    }
+    const double Qh = ldexp(fx_parts_value(H, L), -F) * dq * dp;
+    const double s = p->renormalize ? Q0 / Qh : 1.0;
+    const fx_t sfix = p->renormalize ? fx_coef(s, F) : ((fx_t)1 << F);
+    *s_used = s;
+    /* FP64 wake of the renormalised profile */
+    for (int i = 0; i < n; ++i) V[i] = 0.0;
+    if (w) {
+        for (int i = 0; i < n; ++i) rho[i] = s * dp * ldexp(cd[i], -F);
+        vfo_wake(p, w, rho, V);
+    }
+    /* rotation, then the renormalisation factor */
+    if (p->rotation == 1) {
+        /* drift along q from q - dtheta*p_j into b */
+        for (int i = 0; i < n; ++i) {
+            const double q = p->q_min + i * dq;
+            for (int j = 0; j < n; ++j) {
+                const double pp = p->p_min + j * dp;
+                const double rx = (q - th * pp - p->q_min) / dq;
+                const double m = floor(rx);
+                fx_t W[4];
+                fx_weights(K, rx - m, F, W);
+                fx_t v = fx_round(fx_interp(psi, n, K, 0, j, (int)m, W), F);
+                if (p->clamp) v = fx_clip(v, fx_node(psi, n, (int)m, j), fx_node(psi, n, (int)m + 1, j));
+                b[(size_t)i * n + j] = v;
+            }
+        }
+        /* RF kick along p from p + dtheta*q_i into a */
+        for (int i = 0; i < n; ++i) {
+            const double q = p->q_min + i * dq;
+            for (int j = 0; j < n; ++j) {
+                const double pp = p->p_min + j * dp;
+                const double ry = (pp + th * q - p->p_min) / dp;
+                const double m = floor(ry);
+                fx_t W[4];
+                fx_weights(K, ry - m, F, W);
+                fx_t v = fx_round(fx_interp(b, n, K, 1, i, (int)m, W), F);
+                if (p->clamp) v = fx_clip(v, fx_node(b, n, i, (int)m), fx_node(b, n, i, (int)m + 1));
+                a[(size_t)i * n + j] = fx_round((fx2_t)v * sfix, F);
+            }
+        }
+    } else {
+        const double c = cos(th), sn = sin(th);
+        for (int i = 0; i < n; ++i) {
+            const double q = p->q_min + i * dq;
+            for (int j = 0; j < n; ++j) {
+                const double pp = p->p_min + j * dp;
+                const double q0 = q * c - pp * sn;
+                const double p0 = q * sn + pp * c;
+                const double rx = (q0 - p->q_min) / dq;
+                const double ry = (p0 - p->p_min) / dp;
+                const double mx = floor(rx), my = floor(ry);
+                const int ix = (int)mx, iy = (int)my;
+                fx_t Wx[4], Wy[4], r[4];
+                fx_weights(K, rx - mx, F, Wx);
+                fx_weights(K, ry - my, F, Wy);
+                for (int ka = 0; ka < K; ++ka)   /* stencil row ix + o_a, summed along p */
+                    r[ka] = fx_round(fx_interp(psi, n, K, 1, ix + stencil_offset(K, ka), iy, Wy), F);
+                fx2_t acc = 0;
+                for (int ka = 0; ka < K; ++ka) acc += (fx2_t)Wx[ka] * r[ka];
+                fx_t v = fx_round(acc, F);
+                if (p->clamp) {
+                    fx_t lo = fx_node(psi, n, ix, iy), hi = lo;
+                    for (int da = 0; da < 2; ++da)
+                        for (int db = 0; db < 2; ++db) {
+                            const fx_t f = fx_node(psi, n, ix + da, iy + db);
+                            if (f < lo) lo = f;
+                            if (f > hi) hi = f;
+                        }
+                    v = v < lo ? lo : (v > hi ? hi : v);
+                }
+                a[(size_t)i * n + j] = fx_round((fx2_t)v * sfix, F);
+            }
+        }
+    }
+    /* kick along p: shift V_i*dtheta/dp split once per column */
+    for (int i = 0; i < n; ++i) {
+        const double shift = V[i] * th / dp;
+        double fl = floor(shift);
+        fx_t W[4];
+        fx_weights(K, shift - fl, F, W);
+        if (fl > 2.0 * n) fl = 2.0 * n;          /* every tap is outside the grid */
+        if (fl < -2.0 * n) fl = -2.0 * n;
+        const int m0 = (int)fl;
+        for (int j = 0; j < n; ++j) {
+            fx_t v = fx_round(fx_interp(a, n, K, 1, i, j + m0, W), F);
+            if (p->clamp) v = fx_clip(v, fx_node(a, n, i, j + m0), fx_node(a, n, i, j + m0 + 1));
+            b[(size_t)i * n + j] = v;
+        }
+    }
+    /* damping/diffusion: out = g_j + sum_o E_o(j) g_{j+o}, o = -1..2, with
+     * the coefficients of vfo_fokker_planck collected per row:
+     * E_-1 = k2 - 2 k1 u_-1, E_0 = -3 k1 u_0 - 2 k2, E_1 = 6 k1 u_1 + k2,
+     * E_2 = -k1 u_2; k1 = beta*dtheta/6, k2 = beta*dtheta/dp^2,
+     * u_o = p_min/dp + (j + o) */
+    const double bt = p->beta * th;
+    const double k1 = bt / 6.0, k2 = bt / (dp * dp), pm = p->p_min / dp;
+    for (int j = 0; j < n; ++j) {
+        const double um = pm + (double)(j - 1), u0 = pm + (double)j, u1 = pm + (double)(j + 1),
+                     u2 = pm + (double)(j + 2);
+        const fx_t E[4] = {fx_coef(k2 - 2.0 * k1 * um, F), fx_coef(-3.0 * k1 * u0 - 2.0 * k2, F),
+                           fx_coef(6.0 * k1 * u1 + k2, F), fx_coef(-k1 * u2, F)};
+        for (int i = 0; i < n; ++i) {
+            fx2_t acc = 0;
+            for (int o = -1; o <= 2; ++o) acc += (fx2_t)E[o + 1] * fx_node(b, n, i, j + o);
+            psi[(size_t)i * n + j] = b[(size_t)i * n + j] + fx_round(acc, F);
+        }
+    }
+}
+
+/* Run nsteps fixed-point steps; *s_final receives the renormalisation
+ * factor of the final state (its physical density is s_final*psi*2^-F).
+ * Returns 0, or -1 when out of memory. */
+int vfo_fix_run(const vfo_params *p, int F, const double *w, fx_t *psi, long nsteps, double Q0, double *s_final)
+{
+    const int n = p->n;
+    const size_t nn = (size_t)n * n;
+    fx_t *work = (fx_t *)malloc(sizeof(fx_t) * 2 * nn);
+    double *dwork = (double *)malloc(sizeof(double) * 4 * (size_t)n);
+    if (!work || !dwork) {
+        free(work);
+        free(dwork);
+        return -1;
+    }
+    double s = 1.0;
+    for (long t = 0; t < nsteps; ++t) vfo_fix_step(p, F, w, psi, Q0, &s, work, dwork);
+    /* factor of the final state */
+    const double Qh = vfo_fix_charge(p, F, psi);
+    *s_final = p->renormalize ? Q0 / Qh : 1.0;
+    free(work);
+    free(dwork);
+    return 0;
+}
