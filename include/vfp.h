@@ -61,12 +61,18 @@ enum {
     VFP_EUNSTABLE = -5   /* explicit damping step unstable for these settings  */
 };
 
-/* Arithmetic of psi and of the wake (Sec. IV.A compares binary32/binary64). */
+/* Arithmetic of psi and of the wake (Sec. IV.A compares binary32/binary64
+ * and fixed point with a chosen number of fractional bits). */
 enum {
     VFP_FP64 = 0,        /* psi, rotation, kick, damping and wake in FP64          */
     VFP_FP32 = 1,        /* psi and the step in FP32, wake FP32 on the vector ALU  */
     VFP_MIXED_BF16 = 2,  /* psi FP32; wake on BF16 matrix cores, hi/lo split       */
-    VFP_MIXED_FP16 = 3   /* psi FP32; wake on FP16 matrix cores, hi/lo split       */
+    VFP_MIXED_FP16 = 3,  /* psi FP32; wake on FP16 matrix cores, hi/lo split       */
+    VFP_FIXED = 4        /* psi as 64-bit fixed point with fix_bits fractional bits
+                            (Sec. III.A, last paragraph): FP64 coefficients
+                            rounded to fix_bits, weighted sums exact in 128-bit
+                            integers rounded once, exact integer charge; wake
+                            FP64 */
 };
 /* Charge renormalisation, moments and CSR power are FP64 in every mode. */
 
@@ -104,6 +110,8 @@ typedef struct vfp_params {
                                  z_re/z_im must be NULL (Sec. II.B models).      */
     double  z_shield;         /* VFP_Z_PARALLEL_PLATES: shielding parameter
                                  Pi > 0 (P = Pi^(2/3)); ignored otherwise         */
+    int32_t fix_bits;         /* VFP_FIXED: fractional bits F, 16..59 (psi0 then
+                                 bounded by |psi| < 2^(61-F)); ignored otherwise  */
 } vfp_params;
 
 /* Impedance models of Sec. II.B in normalised form (kappa = k sigma_z0, all
@@ -124,7 +132,8 @@ typedef struct vfp_batch vfp_sim;     /* a single simulation: a set of one     *
 
 /* Defaults: n = 256, [-8, 8]^2, 1000 steps per period, beta = 1e-3, K = 4,
  * no clamp, renormalize = 1, VFP_FP32, padding = 2, standard rotation,
- * zero current, Gaussian start, max_steps = 0, VFP_Z_SAMPLES, z_shield = 1. */
+ * zero current, Gaussian start, max_steps = 0, VFP_Z_SAMPLES, z_shield = 1,
+ * fix_bits = 44. */
 void vfp_params_init(vfp_params *p);
 
 /* The impedance samples a simulation with z_model = `model` uses: Z_k at
@@ -208,6 +217,16 @@ int vfp_batch_record(vfp_batch *b, int32_t every, int64_t cap);
 int vfp_batch_read_record(vfp_batch *b, int32_t i, double *out, int64_t *rows);
 int vfp_batch_steps_done(vfp_batch *b, int32_t i, int64_t *steps);
 void vfp_batch_destroy(vfp_batch *b);
+
+/* The stored density of simulation i exactly as held on the device, for
+ * bit-exact checks and checkpoints: n*n values of the storage type (double
+ * for VFP_FP64, int64_t raw values with fix_bits fractional bits for
+ * VFP_FIXED, float otherwise; index i*n+j) copied to the host buffer out,
+ * which must hold n*n*8 bytes (n*n*4 for the FP32 storage).  The physical
+ * density is *s times the stored one; s is Q0 / Q of the stored density
+ * (1 with renormalize = 0), computed from the exact integer charge in the
+ * fixed-point form.  Synchronises the batch's stream. */
+int vfp_batch_get_raw(vfp_batch *b, int32_t i, void *out, double *s);
 
 /* Launch tuning: columns per work unit are chosen per grid size.  cells is
  * the number of phase-space cells one workgroup owns (0 restores the

@@ -24,6 +24,7 @@
 #include "vfp_step32b.hpp"
 #include "vfp_step32c.hpp"
 #include "vfp_impedance.hpp"
+#include "vfp_stepfix.hpp"
 
 using namespace vfp;
 
@@ -105,11 +106,14 @@ int choose_strip_c(int n, int cells, int rotation)
 
 // a density must be finite and, in the FP32-storage forms, representable in
 // binary32, with a positive, finite charge (the moments are charge-weighted)
-const char *density_error(const double *psi, size_t nn, int precision)
+const char *density_error(const double *psi, size_t nn, int precision, int fix_bits)
 {
-    const double lim = precision == VFP_FP64 ? DBL_MAX : (double)FLT_MAX;
+    const double lim = precision == VFP_FP64    ? DBL_MAX
+                       : precision == VFP_FIXED ? std::ldexp(1.0, 61 - fix_bits)
+                                                : (double)FLT_MAX;
     double sum = 0.0;
     for (size_t z = 0; z < nn; ++z) {
+        if (precision == VFP_FIXED && !(std::fabs(psi[z]) < lim)) return "psi must be finite with |psi| < 2^(61-fix_bits)";
         if (!(std::fabs(psi[z]) <= lim))
             return precision == VFP_FP64 ? "psi must be finite" : "psi must be finite and within the binary32 range";
         sum += psi[z];
@@ -131,7 +135,8 @@ int validate(const vfp_params &p, std::string &why)
     if (p.interp != 3 && p.interp != 4) { why = "interp must be 3 or 4"; return VFP_EINVAL; }
     if (p.clamp != 0 && p.clamp != 1) { why = "clamp must be 0 or 1"; return VFP_EINVAL; }
     if (p.renormalize != 0 && p.renormalize != 1) { why = "renormalize must be 0 or 1"; return VFP_EINVAL; }
-    if (p.precision < VFP_FP64 || p.precision > VFP_MIXED_FP16) { why = "unknown precision"; return VFP_EINVAL; }
+    if (p.precision < VFP_FP64 || p.precision > VFP_FIXED) { why = "unknown precision"; return VFP_EINVAL; }
+    if (p.precision == VFP_FIXED && (p.fix_bits < 16 || p.fix_bits > 59)) { why = "fix_bits must be in [16, 59]"; return VFP_EINVAL; }
     if (p.padding < 2 || (int64_t)p.padding * p.n > (1 << 24)) { why = "padding must be >= 2"; return VFP_EINVAL; }
     if (p.rotation != VFP_ROT_STANDARD && p.rotation != VFP_ROT_MANHATTAN) { why = "unknown rotation"; return VFP_EINVAL; }
     if ((p.z_re == nullptr) != (p.z_im == nullptr)) { why = "z_re and z_im must both be set or both NULL"; return VFP_EINVAL; }
@@ -158,7 +163,7 @@ int validate(const vfp_params &p, std::string &why)
             }
     }
     if (p.psi0) {
-        if (const char *e = density_error(p.psi0, (size_t)p.n * p.n, p.precision)) {
+        if (const char *e = density_error(p.psi0, (size_t)p.n * p.n, p.precision, p.fix_bits)) {
             why = std::string("psi0: ") + e;
             return VFP_EINVAL;
         }
@@ -166,7 +171,12 @@ int validate(const vfp_params &p, std::string &why)
     return VFP_OK;
 }
 
-size_t elem_size(int precision) { return precision == VFP_FP64 ? 8 : 4; }
+size_t elem_size(int precision) { return precision == VFP_FP64 || precision == VFP_FIXED ? 8 : 4; }
+bool is_mixed(int precision) { return precision == VFP_MIXED_BF16 || precision == VFP_MIXED_FP16; }
+// FP32 storage: the staged kernels and a separate wake kernel apply
+bool is_fp32_storage(int precision) { return precision == VFP_FP32 || is_mixed(precision); }
+// bytes of the per-column sums: FP64 sums, or {high, low} integer sums in fixed point
+size_t cs_bytes(int precision, int n) { return (precision == VFP_FIXED ? 2 : 1) * (size_t)n * 8; }
 
 // arena layout for count simulations; fills offsets when hs != nullptr
 size_t layout(const vfp_params *p, int count, std::vector<HostSim> *hs)
@@ -180,11 +190,11 @@ size_t layout(const vfp_params *p, int count, std::vector<HostSim> *hs)
         HostSim &h = hs ? (*hs)[s] : tmp;
         h.nb = nb;
         for (int b = 0; b < 2; ++b) { h.off_psi[b] = off; off = align_up(off + n * n * es); }
-        for (int b = 0; b < 2; ++b) { h.off_cs[b] = off; off = align_up(off + n * 8); }
+        for (int b = 0; b < 2; ++b) { h.off_cs[b] = off; off = align_up(off + cs_bytes(q.precision, q.n)); }
         h.off_wl64 = off; off = align_up(off + (2 * n - 1) * 8);
         h.off_wl32 = off; off = align_up(off + (2 * n - 1) * 4);
         h.off_frag = off;
-        if (q.precision >= VFP_MIXED_BF16) off = align_up(off + (size_t)4 * wake_rev_len(q.n) * sizeof(uint16_t));
+        if (is_mixed(q.precision)) off = align_up(off + (size_t)4 * wake_rev_len(q.n) * sizeof(uint16_t));
         h.off_vext = off; off = align_up(off + n * 4);
         h.off_sext = off; off = align_up(off + 2 * 8);
         h.off_rho = off; off = align_up(off + n * 8);
@@ -330,7 +340,7 @@ int rebuild_units(vfp_batch *b)
     if (!b->active.empty()) rc = upload(b->d_active, b->active.data(), sizeof(int) * b->active.size(), b->stream);
     if (rc) return rc;
     // kernel choice and LDS of the fused step
-    b->fast = b->staged > 0 && b->precision != VFP_FP64 && !b->active.empty();
+    b->fast = b->staged > 0 && is_fp32_storage(b->precision) && !b->active.empty();
     for (int s : b->active) b->fast = b->fast && b->hs[s].fast;
     size_t mx = 0;
     for (const Unit &u : b->units) {
@@ -355,7 +365,7 @@ int rebuild_units(vfp_batch *b)
     // matrix-core wake tiles
     b->wtiles.clear();
     b->lds_wake = 0;
-    if (b->precision != VFP_FP64) {
+    if (is_fp32_storage(b->precision)) {
       for (int g = 0; g < b->ngroups; ++g) {
         b->tile_off[g] = b->wtiles.size();
         for (int s : b->active) {
@@ -395,7 +405,10 @@ int rebuild_units(vfp_batch *b)
 template <typename T, int K, int WAKE, bool CL, int ROT>
 void launch_step_t(vfp_batch *b, int parity)
 {
-    auto k = step_kernel<T, K, WAKE, CL, ROT>;
+    auto k = [] {
+        if constexpr (std::is_same_v<T, int64_t>) return stepfix_kernel<K, WAKE, CL, ROT>;
+        else return step_kernel<T, K, WAKE, CL, ROT>;
+    }();
     static int cur = 0;
     lds_limit(k, b->lds_step, cur);
     hipLaunchKernelGGL(k, dim3((unsigned)b->cur_nunits), dim3(kThreads), b->lds_step, b->cur_stream,
@@ -469,7 +482,7 @@ int launch_tick_group(vfp_batch *b, int parity)
     if (b->cur_nunits == 0) return VFP_OK;
     const bool wake = any_wake(b);
     int t0 = -1, t1 = -1, t2 = -1;
-    const bool mfma = b->precision != VFP_FP64 && wake;      // a separate wake kernel
+    const bool mfma = is_fp32_storage(b->precision) && wake;      // a separate wake kernel
     if (b->timing) {
         int rc = timing_event(b, &t0);
         if (rc) return rc;
@@ -477,6 +490,9 @@ int launch_tick_group(vfp_batch *b, int parity)
     if (b->precision == VFP_FP64) {
         if (wake) launch_step_k<double, WAKE_FUSED>(b, parity);
         else launch_step_k<double, WAKE_NONE>(b, parity);
+    } else if (b->precision == VFP_FIXED) {
+        if (wake) launch_step_k<int64_t, WAKE_FUSED>(b, parity);
+        else launch_step_k<int64_t, WAKE_NONE>(b, parity);
     } else if (!wake) {
         launch_step_k<float, WAKE_NONE>(b, parity);
     } else if (b->precision == VFP_FP32) {
@@ -567,6 +583,11 @@ int launch_stats(vfp_batch *b, const int *d_which, const int *d_buf, int cnt, in
         static int cur = 0;
         lds_limit(stats_kernel<double>, b->lds_stats, cur);
         hipLaunchKernelGGL(stats_kernel<double>, dim3(cnt), dim3(kThreads), b->lds_stats, b->stream, b->d_sd,
+                           d_which, d_buf, b->rec_base, b->every, record);
+    } else if (b->precision == VFP_FIXED) {
+        static int cur = 0;
+        lds_limit(stats_kernel<int64_t>, b->lds_stats, cur);
+        hipLaunchKernelGGL(stats_kernel<int64_t>, dim3(cnt), dim3(kThreads), b->lds_stats, b->stream, b->d_sd,
                            d_which, d_buf, b->rec_base, b->every, record);
     } else {
         static int cur = 0;
@@ -738,6 +759,20 @@ void free_batch(vfp_batch *b)
     delete b;
 }
 
+// column sums of the stored density of the simulation named in d_idx[0], buffer buf
+int launch_project(vfp_batch *b, int n, int buf)
+{
+    const unsigned cb = (unsigned)((n + kWaves - 1) / kWaves);
+    if (b->precision == VFP_FP64)
+        hipLaunchKernelGGL(project_kernel<double>, dim3(cb, 1), dim3(kThreads), 0, b->stream, b->d_sd, b->d_idx, buf);
+    else if (b->precision == VFP_FIXED)
+        hipLaunchKernelGGL(projectfix_kernel, dim3(cb, 1), dim3(kThreads), 0, b->stream, b->d_sd, b->d_idx, buf);
+    else
+        hipLaunchKernelGGL(project_kernel<float>, dim3(cb, 1), dim3(kThreads), 0, b->stream, b->d_sd, b->d_idx, buf);
+    HIPCHK(hipGetLastError());
+    return VFP_OK;
+}
+
 int upload_psi(vfp_batch *b, int s, const double *psi, bool gaussian)
 {
     const HostSim &h = b->hs[s];
@@ -765,23 +800,44 @@ int upload_psi(vfp_batch *b, int s, const double *psi, bool gaussian)
     const int buf = h.active ? b->parity : h.frozen_buf;
     void *dst = b->arena + h.off_psi[buf];
     const unsigned blocks = (unsigned)((nn + kThreads - 1) / kThreads);
+    const int fixb = b->sd[s].fixb;
     if (b->precision == VFP_FP64)
         hipLaunchKernelGGL(import_kernel<double>, dim3(blocks), dim3(kThreads), 0, b->stream, b->d_stage,
-                           (double *)dst, nn);
+                           (double *)dst, nn, fixb);
+    else if (b->precision == VFP_FIXED)
+        hipLaunchKernelGGL(import_kernel<int64_t>, dim3(blocks), dim3(kThreads), 0, b->stream, b->d_stage,
+                           (int64_t *)dst, nn, fixb);
     else
         hipLaunchKernelGGL(import_kernel<float>, dim3(blocks), dim3(kThreads), 0, b->stream, b->d_stage,
-                           (float *)dst, nn);
+                           (float *)dst, nn, fixb);
     HIPCHK(hipGetLastError());
     // column sums of the new state, then Q0 = dq*dp*sum from the device
     const int v[2] = {s, buf};
     rc = upload(b->d_idx, v, sizeof(v), b->stream);
     if (rc) return rc;
-    const unsigned cb = (unsigned)((n + kWaves - 1) / kWaves);
-    if (b->precision == VFP_FP64)
-        hipLaunchKernelGGL(project_kernel<double>, dim3(cb, 1), dim3(kThreads), 0, b->stream, b->d_sd, b->d_idx, buf);
-    else
-        hipLaunchKernelGGL(project_kernel<float>, dim3(cb, 1), dim3(kThreads), 0, b->stream, b->d_sd, b->d_idx, buf);
-    HIPCHK(hipGetLastError());
+    rc = launch_project(b, n, buf);
+    if (rc) return rc;
+    if (b->precision == VFP_FIXED) {
+        // Q0 of the stored (rounded) density from its exact integer sum, as every step takes it
+        std::vector<int64_t> parts(2 * (size_t)n);
+        HIPCHK(hipMemcpyAsync(parts.data(), b->arena + h.off_cs[buf], cs_bytes(VFP_FIXED, n), hipMemcpyDeviceToHost,
+                              b->stream));
+        HIPCHK(hipStreamSynchronize(b->stream));
+        int64_t H = 0, L = 0;
+        for (int i = 0; i < n; ++i) {
+            H += parts[2 * i];
+            L += parts[2 * i + 1];
+        }
+        const double Q0 = std::ldexp((double)H * 4294967296.0 + (double)L, -fixb) * b->sd[s].dq * b->sd[s].dp;
+        if (!(Q0 > 0.0) || !std::isfinite(Q0))
+            return fail(VFP_EINVAL, "initial density must have a positive, finite charge");
+        b->sd[s].Q0 = Q0;
+        b->sd[s].step0 = b->tick;
+        rc = upload_sims(b);
+        if (rc) return rc;
+        b->graph_valid = false;
+        return VFP_OK;
+    }
     // Q0 = dq*dp*sum(psi0) of the FP64 input (stat[0] is scratch here)
     double *q0dev = (double *)(b->arena + h.off_stat);
     hipLaunchKernelGGL(charge64_kernel, dim3(1), dim3(kThreads), 0, b->stream, b->d_stage, nn,
@@ -893,6 +949,7 @@ int create_impl(const vfp_params *p, int32_t count, void *stream, void *ws, size
         d.renorm = q.renormalize;
         d.has_wake = (p[s].z_re != nullptr || p[s].z_model != VFP_Z_SAMPLES) ? 1 : 0;
         d.M = q.padding * q.n;
+        d.fixb = q.precision == VFP_FIXED ? q.fix_bits : 0;
         d.q_min = q.q_min;
         d.p_min = q.p_min;
         d.dq = (q.q_max - q.q_min) / (q.n - 1);
@@ -1048,12 +1105,16 @@ int get_psi_impl(vfp_batch *b, int s, double *psi)
     if (rc) return rc;
     const int buf = h.active ? b->parity : h.frozen_buf;
     const unsigned blocks = (unsigned)((nn + kThreads - 1) / kThreads);
+    const int fixb = b->sd[s].fixb;
     if (b->precision == VFP_FP64)
         hipLaunchKernelGGL(export_kernel<double>, dim3(blocks), dim3(kThreads), 0, b->stream,
-                           (const double *)(b->arena + h.off_psi[buf]), stat_ptr(b, s), b->d_stage, nn);
+                           (const double *)(b->arena + h.off_psi[buf]), stat_ptr(b, s), b->d_stage, nn, fixb);
+    else if (b->precision == VFP_FIXED)
+        hipLaunchKernelGGL(export_kernel<int64_t>, dim3(blocks), dim3(kThreads), 0, b->stream,
+                           (const int64_t *)(b->arena + h.off_psi[buf]), stat_ptr(b, s), b->d_stage, nn, fixb);
     else
         hipLaunchKernelGGL(export_kernel<float>, dim3(blocks), dim3(kThreads), 0, b->stream,
-                           (const float *)(b->arena + h.off_psi[buf]), stat_ptr(b, s), b->d_stage, nn);
+                           (const float *)(b->arena + h.off_psi[buf]), stat_ptr(b, s), b->d_stage, nn, fixb);
     HIPCHK(hipGetLastError());
     HIPCHK(hipMemcpyAsync(psi, b->d_stage, nn * sizeof(double), hipMemcpyDeviceToHost, b->stream));
     HIPCHK(hipStreamSynchronize(b->stream));
@@ -1132,6 +1193,7 @@ void vfp_params_init(vfp_params *p)
     p->max_steps = 0;
     p->z_model = VFP_Z_SAMPLES;
     p->z_shield = 1.0;
+    p->fix_bits = 44;
 }
 
 size_t vfp_params_sizeof(void) { return sizeof(vfp_params); }
@@ -1244,13 +1306,26 @@ int vfp_batch_get_psi(vfp_batch *b, int32_t i, double *psi)
     return get_psi_impl(b, i, psi);
 }
 
+int vfp_batch_get_raw(vfp_batch *b, int32_t i, void *out, double *sfac)
+{
+    if (!b || !out || !sfac || i < 0 || i >= b->count) return fail(VFP_EINVAL, "invalid arguments");
+    int rc = refresh_stats(b);
+    if (rc) return rc;
+    const HostSim &h = b->hs[i];
+    const size_t nn = (size_t)h.p.n * h.p.n;
+    const int buf = h.active ? b->parity : h.frozen_buf;
+    HIPCHK(hipMemcpy(out, b->arena + h.off_psi[buf], nn * elem_size(b->precision), hipMemcpyDeviceToHost));
+    HIPCHK(hipMemcpy(sfac, stat_ptr(b, i) + 6, sizeof(double), hipMemcpyDeviceToHost));
+    return check_finite(b, i);
+}
+
 int vfp_get_psi(vfp_sim *sim, double *psi) { return vfp_batch_get_psi(sim, 0, psi); }
 
 int vfp_batch_set_psi(vfp_batch *b, int32_t i, const double *psi)
 {
     if (!b || !psi || i < 0 || i >= b->count) return fail(VFP_EINVAL, "invalid arguments");
     const size_t nn = (size_t)b->hs[i].p.n * b->hs[i].p.n;
-    if (const char *e = density_error(psi, nn, b->precision)) return fail(VFP_EINVAL, e);
+    if (const char *e = density_error(psi, nn, b->precision, b->sd[i].fixb)) return fail(VFP_EINVAL, e);
     HIPCHK(hipStreamSynchronize(b->stream));
     const int rc = upload_psi(b, i, psi, false);
     if (rc) return rc;
@@ -1264,7 +1339,7 @@ int vfp_batch_set_psi(vfp_batch *b, int32_t i, const double *psi)
             HIPCHK(hipMemcpyAsync(b->arena + b->hs[i].off_psi[b->parity], b->arena + b->hs[i].off_psi[b->hs[i].frozen_buf],
                                   nn * es, hipMemcpyDeviceToDevice, b->stream));
             HIPCHK(hipMemcpyAsync(b->arena + b->hs[i].off_cs[b->parity], b->arena + b->hs[i].off_cs[b->hs[i].frozen_buf],
-                                  b->hs[i].p.n * sizeof(double), hipMemcpyDeviceToDevice, b->stream));
+                                  cs_bytes(b->precision, b->hs[i].p.n), hipMemcpyDeviceToDevice, b->stream));
             HIPCHK(hipStreamSynchronize(b->stream));
         }
     }
@@ -1382,6 +1457,11 @@ int vfp_batch_haissinski(vfp_batch *b, int32_t i, int32_t iters, double alpha)
         lds_limit(haissinski_kernel<double>, lds, cur);
         hipLaunchKernelGGL(haissinski_kernel<double>, dim3(1), dim3(kThreads), lds, b->stream, b->d_sd, i, buf, iters,
                            alpha);
+    } else if (b->precision == VFP_FIXED) {
+        static int cur = 0;
+        lds_limit(haissinski_kernel<int64_t>, lds, cur);
+        hipLaunchKernelGGL(haissinski_kernel<int64_t>, dim3(1), dim3(kThreads), lds, b->stream, b->d_sd, i, buf,
+                           iters, alpha);
     } else {
         static int cur = 0;
         lds_limit(haissinski_kernel<float>, lds, cur);
@@ -1392,12 +1472,8 @@ int vfp_batch_haissinski(vfp_batch *b, int32_t i, int32_t iters, double alpha)
     const int v[2] = {i, buf};
     int rc = upload(b->d_idx, v, sizeof(v), b->stream);
     if (rc) return rc;
-    const unsigned cb = (unsigned)((n + kWaves - 1) / kWaves);
-    if (b->precision == VFP_FP64)
-        hipLaunchKernelGGL(project_kernel<double>, dim3(cb, 1), dim3(kThreads), 0, b->stream, b->d_sd, b->d_idx, buf);
-    else
-        hipLaunchKernelGGL(project_kernel<float>, dim3(cb, 1), dim3(kThreads), 0, b->stream, b->d_sd, b->d_idx, buf);
-    HIPCHK(hipGetLastError());
+    rc = launch_project(b, n, buf);
+    if (rc) return rc;
     HIPCHK(hipStreamSynchronize(b->stream));
     b->sd[i].step0 = b->tick;
     h.steps = 0;
@@ -1414,6 +1490,7 @@ int vfp_batch_seed(vfp_batch *b, int32_t dst, int32_t src)
     const vfp_params &a = b->hs[dst].p, &c = b->hs[src].p;
     if (a.n != c.n || a.q_min != c.q_min || a.q_max != c.q_max || a.p_min != c.p_min || a.p_max != c.p_max)
         return fail(VFP_EINVAL, "seeding needs the same grid");
+    if (b->sd[dst].fixb != b->sd[src].fixb) return fail(VFP_EINVAL, "seeding needs the same fix_bits");
     HIPCHK(hipStreamSynchronize(b->stream));
     HostSim &hd = b->hs[dst];
     const HostSim &hsrc = b->hs[src];
@@ -1426,7 +1503,7 @@ int vfp_batch_seed(vfp_batch *b, int32_t dst, int32_t src)
     const size_t nn = (size_t)a.n * a.n, es = elem_size(b->precision);
     HIPCHK(hipMemcpyAsync(b->arena + hd.off_psi[bd], b->arena + hsrc.off_psi[bs], nn * es, hipMemcpyDeviceToDevice,
                           b->stream));
-    HIPCHK(hipMemcpyAsync(b->arena + hd.off_cs[bd], b->arena + hsrc.off_cs[bs], a.n * sizeof(double),
+    HIPCHK(hipMemcpyAsync(b->arena + hd.off_cs[bd], b->arena + hsrc.off_cs[bs], cs_bytes(b->precision, a.n),
                           hipMemcpyDeviceToDevice, b->stream));
     // the copied density is the source's stored one: its physical state is s*psi^ with the
     // source's Q0, which the destination takes over
@@ -1494,11 +1571,12 @@ int vfp_batch_autotune(vfp_batch *b, int32_t ticks, int32_t *chosen_cells, int32
     for (int s = 0; s < b->count; ++s) {
         const HostSim &h = b->hs[s];
         const size_t nn = (size_t)h.p.n * h.p.n;
-        save[s].resize(2 * nn * es + 2 * h.p.n * 8);
+        const size_t cb = cs_bytes(b->precision, h.p.n);
+        save[s].resize(2 * nn * es + 2 * cb);
         HIPCHK(hipMemcpy(save[s].data(), b->arena + h.off_psi[0], nn * es, hipMemcpyDeviceToHost));
         HIPCHK(hipMemcpy(save[s].data() + nn * es, b->arena + h.off_psi[1], nn * es, hipMemcpyDeviceToHost));
-        HIPCHK(hipMemcpy(save[s].data() + 2 * nn * es, b->arena + h.off_cs[0], h.p.n * 8, hipMemcpyDeviceToHost));
-        HIPCHK(hipMemcpy(save[s].data() + 2 * nn * es + h.p.n * 8, b->arena + h.off_cs[1], h.p.n * 8, hipMemcpyDeviceToHost));
+        HIPCHK(hipMemcpy(save[s].data() + 2 * nn * es, b->arena + h.off_cs[0], cb, hipMemcpyDeviceToHost));
+        HIPCHK(hipMemcpy(save[s].data() + 2 * nn * es + cb, b->arena + h.off_cs[1], cb, hipMemcpyDeviceToHost));
     }
     const int64_t tick0 = b->tick;
     const int parity0 = b->parity;
@@ -1507,7 +1585,7 @@ int vfp_batch_autotune(vfp_batch *b, int32_t ticks, int32_t *chosen_cells, int32
     const int staged0 = b->staged, cells0 = b->cells;
     b->every = 0;   // no records during trials
     b->timing = false;
-    std::vector<int> layouts = b->precision == VFP_FP64 ? std::vector<int>{0} : std::vector<int>{1, 2, 3};
+    std::vector<int> layouts = is_fp32_storage(b->precision) ? std::vector<int>{1, 2, 3} : std::vector<int>{0};
     std::vector<int> cand = {2048, 4096, 8192, 16384};
     hipEvent_t e0, e1;
     HIPCHK(hipEventCreate(&e0));
@@ -1544,8 +1622,9 @@ int vfp_batch_autotune(vfp_batch *b, int32_t ticks, int32_t *chosen_cells, int32
         const size_t nn = (size_t)h.p.n * h.p.n;
         HIPCHK(hipMemcpy(b->arena + h.off_psi[0], save[s].data(), nn * es, hipMemcpyHostToDevice));
         HIPCHK(hipMemcpy(b->arena + h.off_psi[1], save[s].data() + nn * es, nn * es, hipMemcpyHostToDevice));
-        HIPCHK(hipMemcpy(b->arena + h.off_cs[0], save[s].data() + 2 * nn * es, h.p.n * 8, hipMemcpyHostToDevice));
-        HIPCHK(hipMemcpy(b->arena + h.off_cs[1], save[s].data() + 2 * nn * es + h.p.n * 8, h.p.n * 8, hipMemcpyHostToDevice));
+        const size_t cb = cs_bytes(b->precision, h.p.n);
+        HIPCHK(hipMemcpy(b->arena + h.off_cs[0], save[s].data() + 2 * nn * es, cb, hipMemcpyHostToDevice));
+        HIPCHK(hipMemcpy(b->arena + h.off_cs[1], save[s].data() + 2 * nn * es + cb, cb, hipMemcpyHostToDevice));
     }
     b->tick = tick0;
     b->parity = parity0;

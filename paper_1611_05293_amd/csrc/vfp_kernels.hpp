@@ -16,6 +16,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 namespace vfp {
 
 constexpr int kThreads = 256;
@@ -26,7 +28,7 @@ enum WakeMode { WAKE_NONE = 0, WAKE_FUSED = 1, WAKE_EXTERNAL = 2 };
 
 struct SimDev {
     int32_t n, K, rotation, clamp;
-    int32_t renorm, has_wake, M, pad0;
+    int32_t renorm, has_wake, M, fixb;   // fixb: fractional bits of the fixed-point storage
     int64_t step0;                   // global tick at which this simulation was at step 0
     double q_min, p_min, dq, dp;
     double c, s, th, bt;             // cos, sin of dtheta; dtheta; beta*dtheta
@@ -65,6 +67,41 @@ struct Unit {
 };
 
 // ---------------------------------------------------------------- helpers
+// value of a stored density element (raw * 2^-F for the fixed-point storage)
+template <typename T>
+__device__ __forceinline__ double stored_value(T v, int fixb)
+{
+    if constexpr (std::is_same_v<T, int64_t>) return ldexp((double)v, -fixb);
+    else return (double)v;
+}
+// a density value rounded to the storage type (ties to even in fixed point)
+template <typename T>
+__device__ __forceinline__ T to_stored(double x, int fixb)
+{
+    if constexpr (std::is_same_v<T, int64_t>) return llrint(ldexp(x, fixb));
+    else return (T)x;
+}
+
+__device__ __forceinline__ int64_t wave_sum_i64(int64_t v)
+{
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+// exact workgroup sum of 64-bit integers (red: at least kWaves entries)
+__device__ __forceinline__ int64_t block_sum_i64(int64_t v, int64_t *red)
+{
+    v = wave_sum_i64(v);
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    __syncthreads();
+    if (lane == 0) red[wv] = v;
+    __syncthreads();
+    int64_t t = 0;
+    for (int k = 0; k < kWaves; ++k) t += red[k];
+    __syncthreads();
+    return t;
+}
+
 __device__ __forceinline__ double wave_sum(double v)
 {
     for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
@@ -528,7 +565,7 @@ __global__ __launch_bounds__(kThreads) void stats_kernel(const SimDev *__restric
     for (int i = wv; i < n; i += kWaves) {
         double a0 = 0.0, a1 = 0.0, a2 = 0.0;
         for (int j = lane; j < n; j += 64) {
-            const double v = (double)f[(size_t)i * n + j];
+            const double v = stored_value(f[(size_t)i * n + j], sd.fixb);
             const double p = sd.p_min + j * sd.dp;
             a0 += v;
             a1 += p * v;
@@ -552,7 +589,19 @@ __global__ __launch_bounds__(kThreads) void stats_kernel(const SimDev *__restric
     sqq = block_sum(sqq, red);
     const double sp = block_sum(spc, red);
     const double spp = block_sum(sppc, red);
-    const double Qh = sd.dq * sd.dp * s0;
+    double Qh = sd.dq * sd.dp * s0;
+    if constexpr (std::is_same_v<T, int64_t>) {
+        // the fixed-point step's factor: exact integer charge from the column sums
+        const int64_t *cs = (const int64_t *)sd.colsum[bufidx[blockIdx.x]];
+        int64_t ph = 0, pl = 0;
+        for (int k = tid; k < n; k += kThreads) {
+            ph += cs[2 * k];
+            pl += cs[2 * k + 1];
+        }
+        const int64_t H = block_sum_i64(ph, (int64_t *)red);
+        const int64_t L = block_sum_i64(pl, (int64_t *)red);
+        Qh = ldexp((double)H * 4294967296.0 + (double)L, -sd.fixb) * sd.dq * sd.dp;
+    }
     const double s = sd.renorm ? sd.Q0 / Qh : 1.0;
     for (int i = tid; i < n; i += kThreads) {
         rho[i] = s * sd.dp * c0[i];
@@ -985,7 +1034,7 @@ __global__ __launch_bounds__(kThreads) void haissinski_kernel(const SimDev *__re
     for (int i = 0; i < n; ++i)
         for (int j = tid; j < n; j += kThreads) {
             const double p = sd.p_min + j * sd.dp;
-            out[(size_t)i * n + j] = (T)(rho[i] * exp(-0.5 * p * p) / (sd.dp * G));
+            out[(size_t)i * n + j] = to_stored<T>(rho[i] * exp(-0.5 * p * p) / (sd.dp * G), sd.fixb);
         }
 }
 
@@ -1001,21 +1050,21 @@ __global__ __launch_bounds__(kThreads) void charge64_kernel(const double *__rest
     if (threadIdx.x == 0) out[0] = t * dqdp;
 }
 
-// psi^ <- (T) psi64 ; used by create and set_psi
+// psi^ <- psi64 in the storage type; used by create and set_psi
 template <typename T>
-__global__ void import_kernel(const double *__restrict__ in, T *__restrict__ out, size_t nn)
+__global__ void import_kernel(const double *__restrict__ in, T *__restrict__ out, size_t nn, int fixb)
 {
     const size_t z = (size_t)blockIdx.x * kThreads + threadIdx.x;
-    if (z < nn) out[z] = (T)in[z];
+    if (z < nn) out[z] = to_stored<T>(in[z], fixb);
 }
 
 // psi64 <- s * psi^ (s from the latest diagnostics)
 template <typename T>
 __global__ void export_kernel(const T *__restrict__ in, const double *__restrict__ stat,
-                              double *__restrict__ out, size_t nn)
+                              double *__restrict__ out, size_t nn, int fixb)
 {
     const size_t z = (size_t)blockIdx.x * kThreads + threadIdx.x;
-    if (z < nn) out[z] = stat[6] * (double)in[z];
+    if (z < nn) out[z] = stat[6] * stored_value(in[z], fixb);
 }
 
 }  // namespace vfp

@@ -17,11 +17,11 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libvfp.so")
 
 VFP_OK, VFP_EINVAL, VFP_ENOMEM, VFP_EDEVICE, VFP_ESTATE, VFP_EUNSTABLE = 0, -1, -2, -3, -4, -5
-FP64, FP32, MIXED_BF16, MIXED_FP16 = 0, 1, 2, 3
+FP64, FP32, MIXED_BF16, MIXED_FP16, FIXED = 0, 1, 2, 3, 4
 ROT_STANDARD, ROT_MANHATTAN = 0, 1
 Z_SAMPLES, Z_PARALLEL_PLATES, Z_FREE_SPACE = 0, 1, 2
 Z_MODELS = {"samples": Z_SAMPLES, "parallel_plate": Z_PARALLEL_PLATES, "free_space": Z_FREE_SPACE}
-PRECISIONS = {"fp64": FP64, "fp32": FP32, "bf16": MIXED_BF16, "fp16": MIXED_FP16}
+PRECISIONS = {"fp64": FP64, "fp32": FP32, "bf16": MIXED_BF16, "fp16": MIXED_FP16, "fixed": FIXED}
 
 _dp = C.POINTER(C.c_double)
 
@@ -34,6 +34,7 @@ class Params(C.Structure):
         ("renormalize", C.c_int32), ("precision", C.c_int32), ("padding", C.c_int32),
         ("rotation", C.c_int32), ("z_re", _dp), ("z_im", _dp), ("z_scale", C.c_double),
         ("psi0", _dp), ("max_steps", C.c_int64), ("z_model", C.c_int32), ("z_shield", C.c_double),
+        ("fix_bits", C.c_int32),
     ]
 
 
@@ -92,6 +93,7 @@ def load():
             "vfp_batch_csr_power": (C.c_int, [h, _dp]),
             "vfp_batch_moments": (C.c_int, [h, _dp]),
             "vfp_batch_get_psi": (C.c_int, [h, C.c_int32, _dp]),
+            "vfp_batch_get_raw": (C.c_int, [h, C.c_int32, C.c_void_p, _dp]),
             "vfp_batch_set_psi": (C.c_int, [h, C.c_int32, _dp]),
             "vfp_batch_record": (C.c_int, [h, C.c_int32, C.c_int64]),
             "vfp_batch_read_record": (C.c_int, [h, C.c_int32, _dp, C.POINTER(C.c_int64)]),
@@ -142,7 +144,7 @@ def _ptr(a):
 def make_params(n=256, q_range=(-8.0, 8.0), p_range=None, steps_per_period=1000, beta=1e-3,
                 interp=4, clamp=0, renormalize=1, precision="fp32", padding=2,
                 rotation=ROT_STANDARD, z_re=None, z_im=None, z_scale=0.0, psi0=None,
-                max_steps=0, z_model="samples", z_shield=1.0):
+                max_steps=0, z_model="samples", z_shield=1.0, fix_bits=44):
     """Returns (Params, keepalive) -- keepalive holds the numpy arrays the
     struct points to until the create call has copied them."""
     p = Params()
@@ -169,6 +171,7 @@ def make_params(n=256, q_range=(-8.0, 8.0), p_range=None, steps_per_period=1000,
     p.max_steps = int(max_steps)
     p.z_model = Z_MODELS[z_model] if isinstance(z_model, str) else int(z_model)
     p.z_shield = float(z_shield)
+    p.fix_bits = int(fix_bits)
     return p, (zr, zi, ps)
 
 
@@ -250,6 +253,16 @@ class Batch:
     def set_psi(self, i: int, psi):
         a = _f64(psi, self.n[i] ** 2)
         _check(load().vfp_batch_set_psi(self._h, i, _ptr(a)))
+
+    def get_raw(self, i: int):
+        """(stored density as held on the device, s): float64, int64 raw
+        fixed-point values or float32 by precision; physical = s * stored
+        (times 2^-fix_bits for the fixed-point storage)."""
+        dt = {FP64: np.float64, FIXED: np.int64}.get(self._key[1], np.float32)
+        out = np.zeros((self.n[i], self.n[i]), dtype=dt)
+        s = C.c_double()
+        _check(load().vfp_batch_get_raw(self._h, i, out.ctypes.data_as(C.c_void_p), C.byref(s)))
+        return out, s.value
 
     def record(self, every: int, cap: int):
         _check(load().vfp_batch_record(self._h, int(every), int(cap)))
@@ -357,6 +370,7 @@ class Sim:
         p, keep = make_params(**params)
         self.n = p.n
         self.M = p.n * p.padding
+        self._precision = p.precision
         self._ws = None
         ws_ptr, ws_bytes = None, 0
         if torch_workspace:
@@ -402,6 +416,14 @@ class Sim:
     def set_psi(self, psi):
         a = _f64(psi, self.n * self.n)
         _check(load().vfp_set_psi(self._h, _ptr(a)))
+
+    def get_raw(self):
+        """(stored density, s) as Batch.get_raw."""
+        dt = {FP64: np.float64, FIXED: np.int64}.get(self._precision, np.float32)
+        out = np.zeros((self.n, self.n), dtype=dt)
+        s = C.c_double()
+        _check(load().vfp_batch_get_raw(self._h, 0, out.ctypes.data_as(C.c_void_p), C.byref(s)))
+        return out, s.value
 
     def record(self, every: int, cap: int):
         _check(load().vfp_record(self._h, int(every), int(cap)))

@@ -46,6 +46,13 @@ def test_params_defaults():
 def test_densities_the_storage_holds_are_accepted():
     assert _ws(n=16, psi0=np.full(256, 1e39), precision="fp64")[0] == 0
     assert _ws(n=16, psi0=np.full(256, 3e38), precision="fp32")[0] == 0
+    assert _ws(n=16, psi0=np.full(256, 3.9), precision="fixed", fix_bits=59)[0] == 0
+
+
+def test_fixed_point_storage_is_eight_bytes():
+    rc1, b64, _ = _ws(n=64, precision="fp64")
+    rc2, bfx, _ = _ws(n=64, precision="fixed")
+    assert rc1 == rc2 == 0 and bfx >= 2 * 64 * 64 * 8 and bfx >= b64
 
 
 def test_device_impedance_models_validate_on_the_host():
@@ -95,6 +102,10 @@ def test_workspace_size_scales_with_grid_and_precision():
     (dict(n=16, psi0=np.zeros(256), renormalize=0), vfp.VFP_EINVAL, "positive, finite charge"),
     (dict(n=16, psi0=-np.ones(256), precision="fp64"), vfp.VFP_EINVAL, "positive, finite charge"),
     (dict(n=16, psi0=np.full(256, 1e307), precision="fp64"), vfp.VFP_EINVAL, "positive, finite charge"),
+    (dict(precision="fixed", fix_bits=15), vfp.VFP_EINVAL, "fix_bits"),
+    (dict(precision="fixed", fix_bits=60), vfp.VFP_EINVAL, "fix_bits"),
+    (dict(n=16, precision="fixed", fix_bits=59, psi0=np.full(256, 4.0)), vfp.VFP_EINVAL, "2^(61-fix_bits)"),
+    (dict(precision=5), vfp.VFP_EINVAL, "precision"),
     (dict(z_model=3), vfp.VFP_EINVAL, "z_model"),
     (dict(z_model="parallel_plate", z_shield=0.0), vfp.VFP_EINVAL, "z_shield"),
     (dict(z_model="parallel_plate", z_shield=float("inf")), vfp.VFP_EINVAL, "z_shield"),

@@ -1,0 +1,129 @@
+"""The fixed-point form on the GPU (Sec. III.A last paragraph, Sec. IV.A)
+against the fixed-point oracle: bit-exact stored integers where no floating
+point sum of the GPU decides an integer (zero current: geometry,
+coefficients and charge are evaluated the same way on both sides).  With
+current the FP64 wake is summed in another order; a wake that differs in
+its last bit moves a kick weight across a rounding boundary with
+probability ~2^(F-53) |fraction difference|, changing that column by about
+one unit of 2^-F per flip, so the stored states are compared to a few
+dozen units: max |raw difference| <= 64 for F <= 44 and rel-L1 <= 64 2^-F
+(plus 1e-14 for the FP64 wake itself at F = 59)."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import OracleParams
+from paper_1611_05293_amd import inputs, vfp
+from gpu_common import oracle_run, rel_l1, small_sim
+
+pytestmark = pytest.mark.gpu
+
+
+def fixed_oracle(sim, F, nsteps):
+    p = OracleParams.from_recipe(sim)
+    zr, zi = sim.impedance()
+    w = None if zr is None else oracle.wake_kernel(zr, zi, sim.padding * sim.n)
+    raw0 = oracle.fix_quantize(F, sim.psi0())
+    return oracle.fix_run(p, F, w, raw0, nsteps, oracle.fix_charge(p, F, raw0))
+
+
+@pytest.mark.parametrize("K", [3, 4])
+@pytest.mark.parametrize("clamp", [0, 1])
+@pytest.mark.parametrize("rotation", [0, 1])
+@pytest.mark.parametrize("n", [37, 48])
+def test_zero_current_is_bit_exact(K, clamp, rotation, n):
+    F = 44
+    sim = small_sim(n=n, K=K, clamp=clamp, rotation=rotation, steps=53 + n, S=0.0, Pi=None)
+    ref, s_ref = fixed_oracle(sim, F, 25)
+    g = vfp.Sim(**vfp.sim_kwargs(sim, precision="fixed", fix_bits=F))
+    g.step(25)
+    raw, s = g.get_raw()
+    assert raw.dtype == np.int64
+    assert np.array_equal(raw, ref), np.abs(raw - ref).max()
+    assert s == s_ref
+
+
+@pytest.mark.parametrize("F", [24, 44, 59])
+def test_with_current_matches_fixed_oracle(F):
+    sims = [small_sim(n=32, steps=80, S=0.4, Pi=0.5, seed=1),
+            small_sim(n=64, steps=160, S=2.0, Pi=2.0, seed=3, lo=-7.0, hi=7.0),
+            small_sim(n=100, steps=250, S=0.9, Pi=0.8, seed=4, lo=-8.0, hi=8.0)]
+    b = vfp.Batch([vfp.sim_kwargs(s, precision="fixed", fix_bits=F) for s in sims])
+    nt = 30
+    b.step(nt)
+    for i, s in enumerate(sims):
+        ref, s_ref = fixed_oracle(s, F, nt)
+        raw, sg = b.get_raw(i)
+        a, r = sg * np.ldexp(raw.astype(np.float64), -F), s_ref * np.ldexp(ref.astype(np.float64), -F)
+        err = rel_l1(a, r)
+        lsb = np.abs(raw - ref).max()
+        print(f"F={F} sim {i} n={s.n}: rel-L1 {err:.3e}, max |d raw| {lsb}")
+        tol = 64 * 2.0 ** -F + 1e-14
+        assert err <= tol
+        assert F > 44 or lsb <= 64
+        assert rel_l1(b.get_psi(i), r) <= tol
+
+
+def test_59_bits_match_the_fp64_oracle():
+    sim = small_sim(n=64, steps=160, S=1.5, Pi=0.7, seed=9, lo=-7.0, hi=7.0)
+    g = vfp.Sim(**vfp.sim_kwargs(sim, precision="fixed", fix_bits=59))
+    g.step(40)
+    ref, _, _, _ = oracle_run(sim, 40)
+    assert rel_l1(g.get_psi(), ref) <= 1e-13
+
+
+def test_graph_replay_and_direct_launches_agree():
+    sims = [small_sim(n=40, seed=1), small_sim(n=56, seed=2, S=1.5)]
+    out = []
+    for graph in (True, False):
+        b = vfp.Batch([vfp.sim_kwargs(s, precision="fixed", fix_bits=40) for s in sims])
+        b.set_tuning(0, graph, 0)
+        b.step(21)
+        out.append([b.get_raw(i)[0] for i in range(2)])
+    for x, y in zip(*out):
+        assert np.array_equal(x, y)
+
+
+def test_raw_state_of_the_other_forms():
+    sim = small_sim(n=32, seed=5)
+    for prec, dt in (("fp64", np.float64), ("fp32", np.float32), ("fp16", np.float32)):
+        g = vfp.Sim(**vfp.sim_kwargs(sim, precision=prec))
+        g.step(7)
+        raw, s = g.get_raw()
+        assert raw.dtype == dt
+        np.testing.assert_allclose(s * raw.astype(np.float64), g.get_psi(), rtol=1e-15, atol=0)
+
+
+def test_data_type_study_on_the_gpu():
+    """Sec. IV.A, table of converged bunch lengths by data type, at the
+    grid of the binary32/binary64 check (128^2, dq = 0.25, 80 periods): 54
+    and 44 fractional bits converge to the binary64 bunch length within
+    1e-6, 34 bits does not."""
+    n, lo, hi, steps = 128, -16.0, 16.0, 500
+    beta = 1.0 / (2 * math.pi * 5.0)
+    psi0 = inputs.quantize16(inputs.gaussian_psi(n, lo, hi, lo, hi, 2.8, 2.8))
+    kw = dict(n=n, q_range=(lo, hi), steps_per_period=steps, beta=beta, interp=4, psi0=psi0)
+    sims = {"fp64": vfp.Sim(precision="fp64", **kw)}
+    for F in (54, 44, 34):
+        sims[F] = vfp.Sim(precision="fixed", fix_bits=F, **kw)
+    sig = {}
+    for k, g in sims.items():
+        g.step(steps * 80)
+        sig[k] = g.moments()[2]
+    dev = {F: abs(sig[F] / sig["fp64"] - 1) for F in (54, 44, 34)}
+    print("converged sigma_q", sig, "relative to binary64", dev)
+    assert dev[54] < 1e-9 and dev[44] < 1e-6 and dev[34] > 1e-6
+
+
+def test_haissinski_start_in_fixed_point():
+    n, F = 64, 44
+    sim = inputs.Sim(n, -6, 6, -6, 6, 150, 0.08, 4, z_scale=3.0, Pi=0.5)
+    p = OracleParams.from_recipe(sim)
+    zr, zi = sim.impedance()
+    ref = oracle.haissinski(p, oracle.wake_kernel(zr, zi, n * 2), 200, 0.5, 1.0)
+    b = vfp.Batch([vfp.sim_kwargs(sim, precision="fixed", fix_bits=F)])
+    b.haissinski(0, 200, 0.5)
+    raw, s = b.get_raw(0)
+    assert np.abs(np.ldexp(raw.astype(np.float64), -F) - ref).max() <= 2.0 ** -F + 1e-12 * ref.max()
