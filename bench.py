@@ -220,16 +220,20 @@ def main():
     # the same workload in the other forms (same steps; no parity pass)
     forms = {}
     if not args.no_forms:
-        for name, fprec, rot in (("fp32", "fp32", 0), ("manhattan_" + prec, prec, 1)):
-            if name.startswith("fp32") and prec == "fp32":
+        # the 8-byte forms (FP64, 44-bit fixed point) run the generic kernel and fewer ticks
+        for name, fprec, rot, extra in (("fp32", "fp32", 0, {}), ("manhattan_" + prec, prec, 1, {}),
+                                        ("fp64", "fp64", 0, {}), ("fixed44", "fixed", 0, {"fix_bits": 44})):
+            if (name.startswith("fp32") and prec == "fp32") or (name == "fp64" and prec == "fp64"):
                 continue
-            fb = vfp.Batch([vfp.sim_kwargs(s_, precision=fprec, rotation=rot) for s_ in sims], stream=stream,
-                           torch_workspace=True)
-            fb.set_tuning(cells_unit, True, args.staged)
+            wide = fprec in ("fp64", "fixed")
+            fsteps = min(args.steps, 50) if wide else args.steps
+            fb = vfp.Batch([vfp.sim_kwargs(s_, precision=fprec, rotation=rot, **extra) for s_ in sims],
+                           stream=stream, torch_workspace=True)
+            fb.set_tuning(0 if wide else cells_unit, True, args.staged)
             fb.set_streams(args.streams)
-            fb.step(min(args.warmup, 20))
-            fr = timed(fb, stream, cells_tick, 8 if fprec == "fp64" else 4, args.steps)
-            forms[name] = {"value": fr["value"], "ms_per_step": fr["ms"] / args.steps,
+            fb.step(min(args.warmup, 5 if wide else 20))
+            fr = timed(fb, stream, cells_tick, 8 if wide else 4, fsteps)
+            forms[name] = {"value": fr["value"], "ms_per_step": fr["ms"] / fsteps, "steps": fsteps,
                            "step_kernel_us": fr["step_us"], "wake_kernel_us": fr["wake_us"],
                            "hbm_frac": fr["achieved"] / HBM_PEAK_GBS}
             log(f"form {name}: {fr['value']:.4e} cell-updates/s, step kernel {fr['step_us']:.1f} us "
