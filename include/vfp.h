@@ -237,8 +237,9 @@ int vfp_batch_get_raw(vfp_batch *b, int32_t i, void *out, double *s);
  * into the damping pass, 3 the staged kernel with 192-row chunks, 16-byte
  * staging, FP32 source displacements and per-row damping coefficients
  * (same arithmetic definition, different evaluation order; returns
- * VFP_EINVAL for other values).  A new batch uses cells_per_unit 8192,
- * graph replay and layout 3. */
+ * VFP_EINVAL for other values).  A new batch uses cells_per_unit 8192
+ * (1024 for VFP_FP64 and 2048 for VFP_FIXED, whose strips take 16 bytes per
+ * cell of LDS), graph replay and layout 3; 0 restores that default. */
 int vfp_batch_set_tuning(vfp_batch *b, int32_t cells_per_unit, int32_t use_graph, int32_t staged);
 
 /* Stream groups: with groups = 2 (the default) the active simulations are
@@ -296,9 +297,10 @@ int vfp_batch_kernel_timing(vfp_batch *b, int32_t enable);
 int vfp_batch_kernel_times(vfp_batch *b, double out[4]);
 
 /* Autotuner: times `ticks` ticks for every candidate (cells per unit in
- * {2048, 4096, 8192, 16384} and, for FP32 storage, the staged layouts 1, 2
- * and 3) with HIP events on the batch's stream, keeps the fastest and returns
- * it.  The state is saved and restored around the trials. */
+ * {2048, 4096, 8192, 16384}, {1024, 2048, 4096, 8192} for the 8-byte forms,
+ * and, for FP32 storage, the staged layouts 1, 2 and 3) with HIP events on
+ * the batch's stream, keeps the fastest and returns it.  The state is saved
+ * and restored around the trials. */
 int vfp_batch_autotune(vfp_batch *b, int32_t ticks, int32_t *chosen_cells, int32_t *chosen_staged);
 
 /* Architecture name of the current device (e.g. "gfx950:sramecc+:xnack-"),

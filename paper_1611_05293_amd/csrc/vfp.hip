@@ -177,6 +177,13 @@ bool is_mixed(int precision) { return precision == VFP_MIXED_BF16 || precision =
 bool is_fp32_storage(int precision) { return precision == VFP_FP32 || is_mixed(precision); }
 // bytes of the per-column sums: FP64 sums, or {high, low} integer sums in fixed point
 size_t cs_bytes(int precision, int n) { return (precision == VFP_FIXED ? 2 : 1) * (size_t)n * 8; }
+// default cells per work unit: the 8-byte forms hold two copies of their strip
+// in LDS (16 bytes per cell), so small strips leave room for several
+// workgroups per CU (measured on the 200-simulation scan)
+int default_cells(int precision)
+{
+    return precision == VFP_FP64 ? 1024 : precision == VFP_FIXED ? 2048 : 8192;
+}
 
 // arena layout for count simulations; fills offsets when hs != nullptr
 size_t layout(const vfp_params *p, int count, std::vector<HostSim> *hs)
@@ -877,7 +884,7 @@ int create_impl(const vfp_params *p, int32_t count, void *stream, void *ws, size
     b->K = p[0].interp;
     b->clamp = p[0].clamp;
     b->rotation = p[0].rotation;
-    b->cells = 8192;
+    b->cells = default_cells(p[0].precision);
     b->stream = (hipStream_t)stream;
     if (!b->stream) {
         // graphs cannot be captured on the null stream: use a stream of our own
@@ -1379,7 +1386,7 @@ void vfp_destroy(vfp_sim *sim) { free_batch(sim); }
 int vfp_batch_set_tuning(vfp_batch *b, int32_t cells_per_unit, int32_t use_graph, int32_t staged)
 {
     if (!b || cells_per_unit < 0) return fail(VFP_EINVAL, "invalid arguments");
-    const int def = 8192;
+    const int def = default_cells(b->precision);
     const int cells = cells_per_unit ? cells_per_unit : def;
     if (cells * elem_size(b->precision) * 2 > 128 * 1024)
         return fail(VFP_EINVAL, "cells_per_unit too large for the workgroup's LDS");
@@ -1586,7 +1593,8 @@ int vfp_batch_autotune(vfp_batch *b, int32_t ticks, int32_t *chosen_cells, int32
     b->every = 0;   // no records during trials
     b->timing = false;
     std::vector<int> layouts = is_fp32_storage(b->precision) ? std::vector<int>{1, 2, 3} : std::vector<int>{0};
-    std::vector<int> cand = {2048, 4096, 8192, 16384};
+    const std::vector<int> cand = elem_size(b->precision) == 8 ? std::vector<int>{1024, 2048, 4096, 8192}
+                                                                : std::vector<int>{2048, 4096, 8192, 16384};
     hipEvent_t e0, e1;
     HIPCHK(hipEventCreate(&e0));
     HIPCHK(hipEventCreate(&e1));

@@ -132,19 +132,26 @@ __device__ __forceinline__ int xcd_unit(int b, int G)
 }
 
 // ----------------------------------------------- Lagrange weights (Sec. III.A)
-// FP64 mirror of the definition: product over the other stencil nodes.
+// FP64 closed forms of the basis over the offsets -1, 0, 1[, 2], with a
+// shared factor a = t(t-1): l_-1 = -a(t-2)/6, l_0 = (t+1)(t-1)(t-2)/2,
+// l_1 = -(t+1)t(t-2)/2, l_2 = a(t+1)/6 for K = 4; t(t-1)/2, 1-t^2,
+// t(t+1)/2 for K = 3.
 template <int K>
 __device__ __forceinline__ void lagrange64(double t, double *l)
 {
-#pragma clang fp contract(off)
-    for (int k = 0; k < K; ++k) {
-        double v = 1.0;
-        for (int kk = 0; kk < K; ++kk) {
-            if (kk == k) continue;
-            const int ok = k - (K - 1) / 2, okk = kk - (K - 1) / 2;
-            v *= (t - okk) / (double)(ok - okk);
-        }
-        l[k] = v;
+    if constexpr (K == 4) {
+        const double a = fma(t, t, -t);               // t(t-1)
+        const double a6 = a * (1.0 / 6.0);
+        const double b2 = fma(a, 0.5, -1.0);          // (t+1)(t-2)/2
+        l[0] = fma(-a6, t, a * (1.0 / 3.0));
+        l[1] = fma(b2, t, -b2);
+        l[2] = -b2 * t;
+        l[3] = fma(a6, t, a6);
+    } else {
+        const double a = fma(t, t, -t);
+        l[0] = 0.5 * a;
+        l[1] = fma(-t, t, 1.0);
+        l[2] = fma(0.5, a, t);
     }
 }
 
@@ -174,36 +181,45 @@ __device__ __forceinline__ T ld_node(const T *__restrict__ f, int n, int i, int 
 }
 
 // ------------------------------------------------- standard rotation, FP64
-// Same expression order as the definition (no FMA contraction) so that the
-// FP64 path tracks a plain FP64 evaluation to rounding.
+// The source point in cells is (i + dx, j + dy) with the displacement in the
+// exact linear form dx = ax0 + i*axi + j*bx, dy = cy0 + i*cyi + j*by; the
+// K x K sum is taken along p first, then along q.
 template <int K, bool CLAMP>
 __device__ double rotate_at64(const double *__restrict__ src, const SimDev &sd, int i, int j)
 {
-#pragma clang fp contract(off)
     const int n = sd.n;
-    const double q = sd.q_min + i * sd.dq;
-    const double pp = sd.p_min + j * sd.dp;
-    const double q0 = q * sd.c - pp * sd.s;
-    const double p0 = q * sd.s + pp * sd.c;
-    const double rx = (q0 - sd.q_min) / sd.dq;
-    const double ry = (p0 - sd.p_min) / sd.dp;
-    const double mx = floor(rx), my = floor(ry);
-    const int ix = (int)mx, iy = (int)my;
+    constexpr int o0 = (K - 1) / 2;
+    const double dx = fma((double)j, sd.bx, fma((double)i, sd.axi, sd.ax0));
+    const double dy = fma((double)j, sd.by, fma((double)i, sd.cyi, sd.cy0));
+    const double fx = floor(dx), fy = floor(dy);
+    const int ix = i + (int)fx, iy = j + (int)fy;
     double lx[K], ly[K];
-    lagrange64<K>(rx - mx, lx);
-    lagrange64<K>(ry - my, ly);
+    lagrange64<K>(dx - fx, lx);
+    lagrange64<K>(dy - fy, ly);
+    double f[K][K];
+    if (ix - o0 >= 0 && ix + K - 1 - o0 < n && iy - o0 >= 0 && iy + K - 1 - o0 < n) {
+        const double *base = src + (size_t)(ix - o0) * n + (iy - o0);
+#pragma unroll
+        for (int a = 0; a < K; ++a)
+#pragma unroll
+            for (int b = 0; b < K; ++b) f[a][b] = base[(size_t)a * n + b];
+    } else {
+#pragma unroll
+        for (int a = 0; a < K; ++a)
+#pragma unroll
+            for (int b = 0; b < K; ++b) f[a][b] = ld_node(src, n, ix - o0 + a, iy - o0 + b);
+    }
     double v = 0.0;
-    for (int a = 0; a < K; ++a)
-        for (int b = 0; b < K; ++b)
-            v += lx[a] * ly[b] * ld_node(src, n, ix + a - (K - 1) / 2, iy + b - (K - 1) / 2);
+#pragma unroll
+    for (int a = 0; a < K; ++a) {
+        double r = ly[0] * f[a][0];
+#pragma unroll
+        for (int b = 1; b < K; ++b) r = fma(ly[b], f[a][b], r);
+        v = a == 0 ? lx[0] * r : fma(lx[a], r, v);
+    }
     if constexpr (CLAMP) {
-        double lo = ld_node(src, n, ix, iy), hi = lo;
-        for (int a = 0; a < 2; ++a)
-            for (int b = 0; b < 2; ++b) {
-                const double f = ld_node(src, n, ix + a, iy + b);
-                lo = f < lo ? f : lo;
-                hi = f > hi ? f : hi;
-            }
+        const double lo = fmin(fmin(f[o0][o0], f[o0][o0 + 1]), fmin(f[o0 + 1][o0], f[o0 + 1][o0 + 1]));
+        const double hi = fmax(fmax(f[o0][o0], f[o0][o0 + 1]), fmax(f[o0 + 1][o0], f[o0 + 1][o0 + 1]));
         v = v < lo ? lo : (v > hi ? hi : v);
     }
     return v;
@@ -374,17 +390,17 @@ __global__ __launch_bounds__(kThreads) void step_kernel(const SimDev *__restrict
     }
     if (tid == 0) sh_s = s;
     __syncthreads();
-    // per-column kick weights (FP32 path): integer base and fraction
-    if constexpr (sizeof(T) == 4) {
-        if (tid < w) {
-            const double sh = sh_shift[tid];
-            const double fl = floor(sh);
-            float l[K];
-            lagrange32<K>((float)(sh - fl), l);
-            for (int k = 0; k < K; ++k) sh_kw[tid][k] = l[k];
-            sh_km[tid] = (int)fl;
-        }
+    // per-column kick weights: integer base and fraction of the shift
+    if (tid < w) {
+        const double sh = sh_shift[tid];
+        const double fl = floor(sh);
+        T l[K];
+        if constexpr (sizeof(T) == 8) lagrange64<K>(sh - fl, (double *)l);
+        else lagrange32<K>((float)(sh - fl), (float *)l);
+        for (int k = 0; k < K; ++k) sh_kw[tid][k] = l[k];
+        sh_km[tid] = (int)fmax(fmin(fl, 1.0e6), -1.0e6);
     }
+    __syncthreads();
     const T sT = (T)sh_s;
 
     // ---- phase R: rotation -> A
@@ -409,10 +425,7 @@ __global__ __launch_bounds__(kThreads) void step_kernel(const SimDev *__restrict
             T l[K];
             int m;
             if constexpr (sizeof(T) == 8) {
-#pragma clang fp contract(off)
-                const double q = sd.q_min + i * sd.dq;
-                const double pp = sd.p_min + j * sd.dp;
-                const double rx = (q - sd.th * pp - sd.q_min) / sd.dq;
+                const double rx = (double)i - sd.tw * (sd.pm + (double)j);
                 const double mf = floor(rx);
                 lagrange64<K>(rx - mf, (double *)l);
                 m = (int)mf;
@@ -441,10 +454,7 @@ __global__ __launch_bounds__(kThreads) void step_kernel(const SimDev *__restrict
             T l[K];
             int m;
             if constexpr (sizeof(T) == 8) {
-#pragma clang fp contract(off)
-                const double q = sd.q_min + i * sd.dq;
-                const double pp = sd.p_min + j * sd.dp;
-                const double ry = (pp + sd.th * q - sd.p_min) / sd.dp;
+                const double ry = (double)j + sd.tk * (sd.q_min / sd.dq + (double)i);
                 const double mf = floor(ry);
                 lagrange64<K>(ry - mf, (double *)l);
                 m = (int)mf;
@@ -462,18 +472,7 @@ __global__ __launch_bounds__(kThreads) void step_kernel(const SimDev *__restrict
     // ---- phase K: kick along p, A -> B
     for_strip(w, n, [&](int c, int j) {
         const T *col = A + (size_t)c * n;
-        T v;
-        if constexpr (sizeof(T) == 8) {
-#pragma clang fp contract(off)
-            const double r = (double)j + sh_shift[c];
-            const double mf = floor(r);
-            double l[K];
-            lagrange64<K>(r - mf, l);
-            v = interp_lds<double, K, CLAMP>((const double *)col, n, (int)mf, l);
-        } else {
-            v = interp_lds<float, K, CLAMP>((const float *)col, n, j + sh_km[c], (const float *)sh_kw[c]);
-        }
-        B[(size_t)c * n + j] = v;
+        B[(size_t)c * n + j] = interp_lds<T, K, CLAMP>(col, n, j + sh_km[c], sh_kw[c]);
     });
     __syncthreads();
 
@@ -486,15 +485,14 @@ __global__ __launch_bounds__(kThreads) void step_kernel(const SimDev *__restrict
         const T f2 = j + 2 < n ? col[j + 2] : T(0);
         T out;
         if constexpr (sizeof(T) == 8) {
-#pragma clang fp contract(off)
-            const double dp = sd.dp;
-            const double g0 = (sd.p_min + (j - 1) * dp) * fm;
-            const double g1 = (sd.p_min + (j + 0) * dp) * f0;
-            const double g2 = (sd.p_min + (j + 1) * dp) * f1;
-            const double g3 = (sd.p_min + (j + 2) * dp) * f2;
-            const double d1 = (-2.0 * g0 - 3.0 * g1 + 6.0 * g2 - g3) / (6.0 * dp);
-            const double d2 = (fm - 2.0 * f0 + f1) / (dp * dp);
-            out = f0 + sd.bt * (d1 + d2);
+            // the same per-row coefficients as the FP32 branch below, in FP64
+            const double u = sd.pm + (double)j;
+            const double k1 = sd.bt / 6.0, k2 = sd.bt / (sd.dp * sd.dp);
+            const double em = fma(-2.0 * k1, u - 1.0, k2);
+            const double e0 = fma(-3.0 * k1, u, -2.0 * k2);
+            const double e1 = fma(6.0 * k1, u + 1.0, k2);
+            const double e2 = -k1 * (u + 2.0);
+            out = f0 + fma(em, fm, fma(e0, f0, fma(e1, f1, e2 * f2)));
         } else {
             // psi + bt*[(-2 g_{j-1} - 3 g_j + 6 g_{j+1} - g_{j+2})/(6dp) + (f_{j-1} - 2 f_j + f_{j+1})/dp^2]
             // with g = p*psi, p_{j+o}/dp = u + o, u = p_min/dp + j
