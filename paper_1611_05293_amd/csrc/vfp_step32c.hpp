@@ -213,7 +213,9 @@ __global__ __launch_bounds__(kThreads) void step32c_kernel(const SimDev *__restr
     float *S = A + (size_t)W * LA;
     float *Dm = S + (size_t)SX * SY;
     const float *__restrict__ src = (const float *)sd.psi[parity];
-    float *__restrict__ dst = (float *)sd.psi[parity ^ 1];
+    // global address space for the stores, so they are global (not flat) stores
+    typedef __attribute__((address_space(1))) float gfloat;
+    gfloat *__restrict__ dst = (gfloat *)sd.psi[parity ^ 1];
     const double *__restrict__ cs = sd.colsum[parity];
     double *__restrict__ cs_next = sd.colsum[parity ^ 1];
 
@@ -476,7 +478,9 @@ __global__ __launch_bounds__(kThreads) void step32c_kernel(const SimDev *__restr
                     for (int r = 0; r < 4; ++r)
                         o[r] = fmaf(C[r][3], g[r + 3], fmaf(C[r][2], g[r + 2], fmaf(C[r][1], g[r + 1], C[r][0] * g[r])));
                 }
-                *(float4 *)(dst + (size_t)(i0 + c) * n + j) = make_float4(o[0], o[1], o[2], o[3]);
+                typedef float f32x4 __attribute__((ext_vector_type(4)));
+                *(__attribute__((address_space(1))) f32x4 *)(dst + (size_t)(i0 + c) * n + j) =
+                    f32x4{o[0], o[1], o[2], o[3]};
                 part = (o[0] + o[1]) + (o[2] + o[3]);
             }
             Sp[(c * nb + b) * 64 + lane] = part;              // the staging buffer is free now
