@@ -140,6 +140,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-parity", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--no-aux", action="store_true", help="skip the timings of the device-side analysis calls")
     ap.add_argument("--plain-steps", type=int, default=20)
     ap.add_argument("--autotune", action="store_true")
     ap.add_argument("--no-forms", action="store_true", help="skip the FP32 and Manhattan forms")
@@ -263,6 +264,38 @@ def main():
                  "steps_per_sim": ps}
         log(f"plain form: {pv:.4e} cell-updates/s; batched speed-up {value / pv:.1f}x")
 
+    # the device-side analysis and set-up calls of a scan, timed per call on the
+    # host clock (synchronous calls: launch, device work and the copy of the result)
+    aux = None
+    if not args.no_aux:
+        import time as _time
+        big = [s_ for s_ in sims if s_.n == 1024][:2]
+        ab = vfp.Batch([vfp.sim_kwargs(s_, precision=prec) for s_ in big], stream=stream, torch_workspace=True)
+        ab.step(5)
+        torch.cuda.synchronize()
+
+        def per_call(fn, reps):
+            fn()
+            t0 = _time.perf_counter()
+            for _ in range(reps):
+                fn()
+            return (_time.perf_counter() - t0) / reps * 1e6
+
+        n1 = big[0]
+        aux = {
+            "unit": "us per call (host clock, synchronous)",
+            "grid": "1024^2, padding 2",
+            "impedance_samples_parallel_plates": per_call(
+                lambda: vfp.impedance_samples(n1.n, n1.padding, n1.q_min, n1.q_max, "parallel_plate", n1.Pi), 5),
+            "csr_spectrum": per_call(lambda: ab.csr_spectrum(0), 10),
+            "haissinski_200_iterations": per_call(lambda: ab.haissinski(1, 200, 0.5), 3),
+            "seed_from_other_simulation": per_call(lambda: ab.seed(1, 0), 10),
+        }
+        ab.close()
+        del ab
+        torch.cuda.empty_cache()
+        log("aux calls (us): " + ", ".join(f"{k} {v:.0f}" for k, v in aux.items() if isinstance(v, float)))
+
     cpu = None
     if not args.no_cpu:
         log("timing the oracle on the host")
@@ -303,6 +336,7 @@ def main():
         "forms": forms,
         "plain": plain,
         "batched_speedup": None if plain is None else value / plain["value"],
+        "aux": aux,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

@@ -127,3 +127,19 @@ def test_haissinski_start_in_fixed_point():
     b.haissinski(0, 200, 0.5)
     raw, s = b.get_raw(0)
     assert np.abs(np.ldexp(raw.astype(np.float64), -F) - ref).max() <= 2.0 ** -F + 1e-12 * ref.max()
+
+
+def test_autotune_keeps_the_fixed_point_state():
+    """The tuner's trials run on saved state: after tuning, a zero-current
+    fixed-point batch continues bit for bit as the oracle."""
+    F = 40
+    sims = [small_sim(n=48, S=0.0, Pi=None, seed=1), small_sim(n=64, S=0.0, Pi=None, seed=2, steps=120)]
+    b = vfp.Batch([vfp.sim_kwargs(s, precision="fixed", fix_bits=F) for s in sims])
+    b.step(3)
+    cells, layout = b.autotune(ticks=2)
+    assert cells in (1024, 2048, 4096, 8192) and layout == 0
+    b.step(5)
+    for i, s in enumerate(sims):
+        ref, s_ref = fixed_oracle(s, F, 8)
+        raw, sg = b.get_raw(i)
+        assert np.array_equal(raw, ref) and sg == s_ref
