@@ -67,7 +67,7 @@ struct HostSim {
     int frozen_buf = 0;      // buffer holding the state once retired
     // arena offsets
     size_t off_psi[2], off_cs[2], off_wl64, off_wl32, off_frag, off_vext, off_sext, off_rho,
-        off_v, off_stat, off_zr;
+        off_v, off_stat, off_zr, off_mom;
     int nb = 0;
     bool fast = false;       // eligible for the LDS-staged FP32 step kernel
 };
@@ -207,6 +207,7 @@ size_t layout(const vfp_params *p, int count, std::vector<HostSim> *hs)
         h.off_rho = off; off = align_up(off + n * 8);
         h.off_v = off; off = align_up(off + n * 8);
         h.off_stat = off; off = align_up(off + 8 * 8);
+        h.off_mom = off; off = align_up(off + 3 * n * 8);
         h.off_zr = off; off = align_up(off + (size_t)(q.padding * q.n / 2 + 1) * 8);
     }
     return off;
@@ -586,22 +587,36 @@ int launch_tick(vfp_batch *b, int parity)
 int launch_stats(vfp_batch *b, const int *d_which, const int *d_buf, int cnt, int record)
 {
     if (cnt == 0) return VFP_OK;
+    // per-column sums over 16-column tiles of the largest grid
+    const int maxn = (int)(b->lds_stats / (2 * sizeof(double)));
+    const dim3 mgrid((unsigned)((maxn + 15) / 16), (unsigned)cnt);
+    if (b->precision == VFP_FP64)
+        hipLaunchKernelGGL(moments_kernel<double>, mgrid, dim3(kThreads), 0, b->stream, b->d_sd, d_which, d_buf);
+    else if (b->precision == VFP_FIXED)
+        hipLaunchKernelGGL(moments_kernel<int64_t>, mgrid, dim3(kThreads), 0, b->stream, b->d_sd, d_which, d_buf);
+    else
+        hipLaunchKernelGGL(moments_kernel<float>, mgrid, dim3(kThreads), 0, b->stream, b->d_sd, d_which, d_buf);
     if (b->precision == VFP_FP64) {
         static int cur = 0;
         lds_limit(stats_kernel<double>, b->lds_stats, cur);
         hipLaunchKernelGGL(stats_kernel<double>, dim3(cnt), dim3(kThreads), b->lds_stats, b->stream, b->d_sd,
-                           d_which, d_buf, b->rec_base, b->every, record);
+                           d_which, d_buf);
     } else if (b->precision == VFP_FIXED) {
         static int cur = 0;
         lds_limit(stats_kernel<int64_t>, b->lds_stats, cur);
         hipLaunchKernelGGL(stats_kernel<int64_t>, dim3(cnt), dim3(kThreads), b->lds_stats, b->stream, b->d_sd,
-                           d_which, d_buf, b->rec_base, b->every, record);
+                           d_which, d_buf);
     } else {
         static int cur = 0;
         lds_limit(stats_kernel<float>, b->lds_stats, cur);
         hipLaunchKernelGGL(stats_kernel<float>, dim3(cnt), dim3(kThreads), b->lds_stats, b->stream, b->d_sd,
-                           d_which, d_buf, b->rec_base, b->every, record);
+                           d_which, d_buf);
     }
+    // the wake of every listed simulation over row tiles of the largest grid, then P
+    const unsigned tiles = (unsigned)((maxn + 63) / 64);
+    hipLaunchKernelGGL(wakev_kernel, dim3(tiles, (unsigned)cnt), dim3(kThreads), 0, b->stream, b->d_sd, d_which);
+    hipLaunchKernelGGL(power_kernel, dim3(cnt), dim3(kThreads), 0, b->stream, b->d_sd, d_which, b->rec_base,
+                       b->every, record);
     HIPCHK(hipGetLastError());
     return VFP_OK;
 }
@@ -1003,6 +1018,7 @@ int create_impl(const vfp_params *p, int32_t count, void *stream, void *ws, size
         d.rho_out = (double *)(A + h.off_rho);
         d.v_out = (double *)(A + h.off_v);
         d.stat = (double *)(A + h.off_stat);
+        d.mom = (double *)(A + h.off_mom);
         d.zr64 = (const double *)(A + h.off_zr);
         // the staged kernel needs n % 4 == 0 and a rotation source within 2 cells of every
         // node; dx, dy are linear in (i, j), so the corners bound them
@@ -1438,7 +1454,8 @@ int vfp_batch_csr_spectrum(vfp_batch *b, int32_t i, double *out)
     const int nk = b->sd[i].M / 2 + 1;
     rc = ensure_stage(b, nk);
     if (rc) return rc;
-    hipLaunchKernelGGL(spectrum_kernel, dim3(1), dim3(kThreads), 0, b->stream, b->d_sd, i, b->d_stage);
+    hipLaunchKernelGGL(spectrum_kernel, dim3((unsigned)((b->sd[i].M / 2 + kThreads) / kThreads)), dim3(kThreads), 0,
+                       b->stream, b->d_sd, i, b->d_stage);
     HIPCHK(hipGetLastError());
     HIPCHK(hipMemcpyAsync(out, b->d_stage, nk * sizeof(double), hipMemcpyDeviceToHost, b->stream));
     HIPCHK(hipStreamSynchronize(b->stream));
@@ -1458,22 +1475,24 @@ int vfp_batch_haissinski(vfp_batch *b, int32_t i, int32_t iters, double alpha)
         b->units_dirty = true;
     }
     const int buf = b->parity, n = h.p.n;
-    const size_t lds = 3 * (size_t)n * sizeof(double);
+    // the wake lags go to LDS as well while the workgroup's LDS holds them
+    const int stage_lags = n <= 2048 ? 1 : 0;
+    const size_t lds = (3 * (size_t)n + (stage_lags ? 2 * (size_t)n - 1 : 0)) * sizeof(double);
     if (b->precision == VFP_FP64) {
         static int cur = 0;
         lds_limit(haissinski_kernel<double>, lds, cur);
         hipLaunchKernelGGL(haissinski_kernel<double>, dim3(1), dim3(kThreads), lds, b->stream, b->d_sd, i, buf, iters,
-                           alpha);
+                           alpha, stage_lags);
     } else if (b->precision == VFP_FIXED) {
         static int cur = 0;
         lds_limit(haissinski_kernel<int64_t>, lds, cur);
         hipLaunchKernelGGL(haissinski_kernel<int64_t>, dim3(1), dim3(kThreads), lds, b->stream, b->d_sd, i, buf,
-                           iters, alpha);
+                           iters, alpha, stage_lags);
     } else {
         static int cur = 0;
         lds_limit(haissinski_kernel<float>, lds, cur);
         hipLaunchKernelGGL(haissinski_kernel<float>, dim3(1), dim3(kThreads), lds, b->stream, b->d_sd, i, buf, iters,
-                           alpha);
+                           alpha, stage_lags);
     }
     HIPCHK(hipGetLastError());
     const int v[2] = {i, buf};

@@ -50,6 +50,7 @@ struct SimDev {
     double *rho_out, *v_out;         // FP64 diagnostics (n each)
     const double *zr64;              // Re Z_k, k = 0..M/2 (CSR spectrum)
     double *stat;                    // {Q, <q>, sq, <p>, sp, P, s, bad}
+    double *mom;                     // per column: sum psi, sum p psi, sum p^2 psi (3n, FP64)
     double *ring;                    // record rows (7 doubles each) or NULL
     int64_t ring_cap;
     int64_t *ring_rows;
@@ -541,26 +542,26 @@ __global__ __launch_bounds__(kThreads) void project_kernel(const SimDev *__restr
 }
 
 // =====================================================================
-// FP64 diagnostics of the current state (one workgroup per simulation):
-// s, rho = s*dp*colsum, V = S*T(w)*rho (FP64 Toeplitz), P = sum rho V,
-// moments; optionally appends a record row.  Also flags a non-finite sum.
-// dynamic LDS: 2n doubles.
+// FP64 diagnostics of the current state, in four launches:
+//   moments_kernel (16 columns per workgroup): per column sum psi,
+//     sum p psi, sum p^2 psi;
+//   stats_kernel (one workgroup per simulation): s, rho = s*dp*colsum and
+//     the moments from the column sums; dynamic LDS: 2n doubles;
+//   wakev_kernel (64 rows per workgroup): V = S*T(w)*rho (FP64 Toeplitz);
+//   power_kernel (one workgroup per simulation): P = sum rho V, the
+//     non-finite flag and, optionally, a record row.
 // =====================================================================
 template <typename T>
-__global__ __launch_bounds__(kThreads) void stats_kernel(const SimDev *__restrict__ sims,
-                                                         const int *__restrict__ which,
-                                                         const int *__restrict__ bufidx,
-                                                         int64_t rec_base, int every, int record)
+__global__ __launch_bounds__(kThreads) void moments_kernel(const SimDev *__restrict__ sims,
+                                                           const int *__restrict__ which,
+                                                           const int *__restrict__ bufidx)
 {
-    extern __shared__ __align__(16) unsigned char smem_raw[];
-    __shared__ double red[kThreads];
-    const SimDev &sd = sims[which[blockIdx.x]];
-    const int n = sd.n, tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-    const T *f = (const T *)sd.psi[bufidx[blockIdx.x]];
-    double *c0 = (double *)smem_raw;       // column sums
-    double *rho = c0 + n;
-    double spc = 0.0, sppc = 0.0;          // per-thread partials of sum p psi, p^2 psi
-    for (int i = wv; i < n; i += kWaves) {
+    const SimDev &sd = sims[which[blockIdx.y]];
+    const int n = sd.n, lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const T *f = (const T *)sd.psi[bufidx[blockIdx.y]];
+    for (int c = 0; c < 4; ++c) {
+        const int i = blockIdx.x * 16 + c * kWaves + wv;
+        if (i >= n) break;
         double a0 = 0.0, a1 = 0.0, a2 = 0.0;
         for (int j = lane; j < n; j += 64) {
             const double v = stored_value(f[(size_t)i * n + j], sd.fixb);
@@ -570,9 +571,32 @@ __global__ __launch_bounds__(kThreads) void stats_kernel(const SimDev *__restric
             a2 += p * p * v;
         }
         a0 = wave_sum(a0);
-        if (lane == 0) c0[i] = a0;
-        spc += a1;
-        sppc += a2;
+        a1 = wave_sum(a1);
+        a2 = wave_sum(a2);
+        if (lane == 0) {
+            sd.mom[3 * i] = a0;
+            sd.mom[3 * i + 1] = a1;
+            sd.mom[3 * i + 2] = a2;
+        }
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kThreads) void stats_kernel(const SimDev *__restrict__ sims,
+                                                         const int *__restrict__ which,
+                                                         const int *__restrict__ bufidx)
+{
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    __shared__ double red[kThreads];
+    const SimDev &sd = sims[which[blockIdx.x]];
+    const int n = sd.n, tid = threadIdx.x;
+    double *c0 = (double *)smem_raw;       // column sums
+    double *rho = c0 + n;
+    double spc = 0.0, sppc = 0.0;          // per-thread partials of sum p psi, p^2 psi
+    for (int i = tid; i < n; i += kThreads) {
+        c0[i] = sd.mom[3 * i];
+        spc += sd.mom[3 * i + 1];
+        sppc += sd.mom[3 * i + 2];
     }
     __syncthreads();
     double s0 = 0.0, sq = 0.0, sqq = 0.0;
@@ -605,24 +629,60 @@ __global__ __launch_bounds__(kThreads) void stats_kernel(const SimDev *__restric
         rho[i] = s * sd.dp * c0[i];
         sd.rho_out[i] = rho[i];
     }
-    __syncthreads();
-    double pw = 0.0;
-    for (int i = tid; i < n; i += kThreads) {
-        double v = 0.0;
-        if (sd.has_wake) {
-            for (int j = 0; j < n; ++j) v += sd.wl64[i - j + n - 1] * rho[j];
-            v *= sd.S;
-        }
-        sd.v_out[i] = v;
-        pw += rho[i] * v;
-    }
-    pw = block_sum(pw, red);
     if (tid == 0) {
         const double mq = sq / s0, mp = sp / s0;
-        const double st[8] = {s * Qh, mq, sqrt(fmax(sqq / s0 - mq * mq, 0.0)), mp,
-                              sqrt(fmax(spp / s0 - mp * mp, 0.0)), pw, s,
-                              (isfinite(s0) && isfinite(pw)) ? 0.0 : 1.0};
-        for (int k = 0; k < 8; ++k) sd.stat[k] = st[k];
+        const double st[7] = {s * Qh, mq, sqrt(fmax(sqq / s0 - mq * mq, 0.0)), mp,
+                              sqrt(fmax(spp / s0 - mp * mp, 0.0)), 0.0, s};
+        for (int k = 0; k < 7; ++k) sd.stat[k] = st[k];
+    }
+}
+
+// V_i = S sum_j w[i-j] rho_j for 64 rows i per workgroup (grid.x: row tiles
+// of the largest grid, grid.y: simulations); the four waves take every
+// fourth j and their sums are added in a fixed order
+__global__ __launch_bounds__(kThreads) void wakev_kernel(const SimDev *__restrict__ sims,
+                                                         const int *__restrict__ which)
+{
+    __shared__ double part[kWaves][64];
+    const SimDev &sd = sims[which[blockIdx.y]];
+    const int n = sd.n, lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int i0 = blockIdx.x * 64;
+    if (i0 >= n) return;
+    const int i = i0 + lane;
+    double v = 0.0;
+    if (sd.has_wake && i < n) {
+        const double *wi = sd.wl64 + i + n - 1;          // wi[-j] = w[i - j]
+        double v0 = 0.0, v1 = 0.0;
+        int j = wv;
+        for (; j + kWaves < n; j += 2 * kWaves) {
+            v0 = fma(wi[-j], sd.rho_out[j], v0);
+            v1 = fma(wi[-j - kWaves], sd.rho_out[j + kWaves], v1);
+        }
+        if (j < n) v0 = fma(wi[-j], sd.rho_out[j], v0);
+        v = v0 + v1;
+    }
+    part[wv][lane] = v;
+    __syncthreads();
+    if (wv == 0 && i < n) sd.v_out[i] = sd.has_wake ? sd.S * ((part[0][lane] + part[1][lane]) + (part[2][lane] + part[3][lane])) : 0.0;
+}
+
+// P = sum_i rho_i V_i, the non-finite flag, and the record row
+__global__ __launch_bounds__(kThreads) void power_kernel(const SimDev *__restrict__ sims,
+                                                         const int *__restrict__ which, int64_t rec_base,
+                                                         int every, int record)
+{
+    __shared__ double red[kThreads];
+    const SimDev &sd = sims[which[blockIdx.x]];
+    const int n = sd.n, tid = threadIdx.x;
+    double pw = 0.0;
+    for (int i = tid; i < n; i += kThreads) pw += sd.rho_out[i] * sd.v_out[i];
+    pw = block_sum(pw, red);
+    if (tid == 0) {
+        double st[7];
+        for (int k = 0; k < 7; ++k) st[k] = sd.stat[k];
+        st[5] = pw;
+        sd.stat[5] = pw;
+        sd.stat[7] = (isfinite(st[0]) && isfinite(pw)) ? 0.0 : 1.0;
         if (record && sd.ring) {
             const int64_t row = *sd.ring_rows;
             if (row < sd.ring_cap) {
@@ -952,13 +1012,13 @@ __global__ __launch_bounds__(kThreads) void wake_vec_kernel(const SimDev *__rest
 // CSR spectrum of the state whose profile the diagnostics kernel left in
 // rho_out (Sec. IV.C): out[k] = (S/M) m_k Re Z_k |rho~_k|^2, k = 0..M/2,
 // rho~_k the DFT of the zero-padded profile, m_k = 2 for the bins that stand
-// for k and M-k.  One workgroup per simulation, threads over k.
+// for k and M-k.  One thread per bin, over as many workgroups as needed.
 __global__ __launch_bounds__(kThreads) void spectrum_kernel(const SimDev *__restrict__ sims, int which,
                                                             double *__restrict__ out)
 {
     const SimDev &sd = sims[which];
     const int n = sd.n, M = sd.M;
-    for (int k = threadIdx.x; k <= M / 2; k += kThreads) {
+    for (int k = blockIdx.x * kThreads + threadIdx.x; k <= M / 2; k += gridDim.x * kThreads) {
         double re = 0.0, im = 0.0;
         for (int j = 0; j < n; ++j) {
             const long long kj = ((long long)k * j) % M;
@@ -976,16 +1036,23 @@ __global__ __launch_bounds__(kThreads) void spectrum_kernel(const SimDev *__rest
 // U' = V[rho], dq*sum(rho) = Q0, solved by the damped fixed-point iteration
 // rho <- (1-alpha) rho + alpha F(rho) from the Gaussian, U by the cumulative
 // trapezoid rule from q_min; psi_ij = rho_i g_j with the unit Gaussian g in p
-// normalised on the grid.  One workgroup; dynamic LDS: 3n doubles.
+// normalised on the grid.  One workgroup; dynamic LDS: 3n doubles, plus the
+// 2n-1 wake lags when stage_lags (the wake sums then read LDS only).
 template <typename T>
 __global__ __launch_bounds__(kThreads) void haissinski_kernel(const SimDev *__restrict__ sims, int which, int buf,
-                                                              int iters, double alpha)
+                                                              int iters, double alpha, int stage_lags)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     __shared__ double red[kThreads];
     const SimDev &sd = sims[which];
     const int n = sd.n, tid = threadIdx.x;
     double *rho = (double *)smem_raw, *V = rho + n, *F = V + n;
+    const double *wl = sd.wl64;
+    if (stage_lags && sd.has_wake) {
+        double *Wl = F + n;
+        for (int k = tid; k < 2 * n - 1; k += kThreads) Wl[k] = sd.wl64[k];
+        wl = Wl;
+    }
     double part = 0.0;
     for (int i = tid; i < n; i += kThreads) {
         const double q = sd.q_min + i * sd.dq;
@@ -997,10 +1064,20 @@ __global__ __launch_bounds__(kThreads) void haissinski_kernel(const SimDev *__re
     __syncthreads();
     for (int it = 0; it < iters; ++it) {
         for (int i = tid; i < n; i += kThreads) {
-            double v = 0.0;
-            if (sd.has_wake)
-                for (int j = 0; j < n; ++j) v += sd.wl64[i - j + n - 1] * rho[j];
-            V[i] = sd.S * v;
+            // four interleaved partial sums over j keep several loads in flight
+            double v0 = 0.0, v1 = 0.0, v2 = 0.0, v3 = 0.0;
+            if (sd.has_wake) {
+                const double *wi = wl + i + n - 1;          // wi[-j] = w[i - j]
+                int j = 0;
+                for (; j + 3 < n; j += 4) {
+                    v0 = fma(wi[-j], rho[j], v0);
+                    v1 = fma(wi[-j - 1], rho[j + 1], v1);
+                    v2 = fma(wi[-j - 2], rho[j + 2], v2);
+                    v3 = fma(wi[-j - 3], rho[j + 3], v3);
+                }
+                for (; j < n; ++j) v0 = fma(wi[-j], rho[j], v0);
+            }
+            V[i] = sd.S * ((v0 + v1) + (v2 + v3));
         }
         __syncthreads();
         if (tid == 0) {                      // cumulative trapezoid, in order
