@@ -781,6 +781,28 @@ void free_batch(vfp_batch *b)
     delete b;
 }
 
+// Haissinski iteration of simulation i (named in d_idx[0]): Gaussian start,
+// then per iteration the wake of the profile over 64-row tiles and one damped
+// update, then psi into buffer buf
+template <typename T>
+int launch_haissinski(vfp_batch *b, int i, int buf, int iters, double alpha)
+{
+    const int n = b->hs[i].p.n;
+    const size_t lds = (size_t)n * sizeof(double);
+    static int cur = 0;
+    lds_limit(haissinski_kernel<T>, lds, cur);
+    hipLaunchKernelGGL(haissinski_kernel<T>, dim3(1), dim3(kThreads), 0, b->stream, b->d_sd, i, buf, 0, alpha);
+    for (int it = 0; it < iters; ++it) {
+        hipLaunchKernelGGL(wakev_kernel, dim3((unsigned)((n + 63) / 64), 1), dim3(kThreads), 0, b->stream, b->d_sd,
+                           b->d_idx);
+        hipLaunchKernelGGL(haissinski_kernel<T>, dim3(1), dim3(kThreads), lds, b->stream, b->d_sd, i, buf, 1, alpha);
+    }
+    hipLaunchKernelGGL(haissinski_kernel<T>, dim3((unsigned)std::min(n, 1024)), dim3(kThreads), 0, b->stream, b->d_sd,
+                       i, buf, 2, alpha);
+    HIPCHK(hipGetLastError());
+    return VFP_OK;
+}
+
 // column sums of the stored density of the simulation named in d_idx[0], buffer buf
 int launch_project(vfp_batch *b, int n, int buf)
 {
@@ -1475,28 +1497,12 @@ int vfp_batch_haissinski(vfp_batch *b, int32_t i, int32_t iters, double alpha)
         b->units_dirty = true;
     }
     const int buf = b->parity, n = h.p.n;
-    // the wake lags go to LDS as well while the workgroup's LDS holds them
-    const int stage_lags = n <= 2048 ? 1 : 0;
-    const size_t lds = (3 * (size_t)n + (stage_lags ? 2 * (size_t)n - 1 : 0)) * sizeof(double);
-    if (b->precision == VFP_FP64) {
-        static int cur = 0;
-        lds_limit(haissinski_kernel<double>, lds, cur);
-        hipLaunchKernelGGL(haissinski_kernel<double>, dim3(1), dim3(kThreads), lds, b->stream, b->d_sd, i, buf, iters,
-                           alpha, stage_lags);
-    } else if (b->precision == VFP_FIXED) {
-        static int cur = 0;
-        lds_limit(haissinski_kernel<int64_t>, lds, cur);
-        hipLaunchKernelGGL(haissinski_kernel<int64_t>, dim3(1), dim3(kThreads), lds, b->stream, b->d_sd, i, buf,
-                           iters, alpha, stage_lags);
-    } else {
-        static int cur = 0;
-        lds_limit(haissinski_kernel<float>, lds, cur);
-        hipLaunchKernelGGL(haissinski_kernel<float>, dim3(1), dim3(kThreads), lds, b->stream, b->d_sd, i, buf, iters,
-                           alpha, stage_lags);
-    }
-    HIPCHK(hipGetLastError());
     const int v[2] = {i, buf};
     int rc = upload(b->d_idx, v, sizeof(v), b->stream);
+    if (rc) return rc;
+    if (b->precision == VFP_FP64) rc = launch_haissinski<double>(b, i, buf, iters, alpha);
+    else if (b->precision == VFP_FIXED) rc = launch_haissinski<int64_t>(b, i, buf, iters, alpha);
+    else rc = launch_haissinski<float>(b, i, buf, iters, alpha);
     if (rc) return rc;
     rc = launch_project(b, n, buf);
     if (rc) return rc;

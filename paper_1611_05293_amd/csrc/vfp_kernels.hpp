@@ -1036,50 +1036,35 @@ __global__ __launch_bounds__(kThreads) void spectrum_kernel(const SimDev *__rest
 // U' = V[rho], dq*sum(rho) = Q0, solved by the damped fixed-point iteration
 // rho <- (1-alpha) rho + alpha F(rho) from the Gaussian, U by the cumulative
 // trapezoid rule from q_min; psi_ij = rho_i g_j with the unit Gaussian g in p
-// normalised on the grid.  One workgroup; dynamic LDS: 3n doubles, plus the
-// 2n-1 wake lags when stage_lags (the wake sums then read LDS only).
+// normalised on the grid.  The iterate lives in rho_out, its wake in v_out
+// (computed between the phases by wakev_kernel); one workgroup per phase:
+//   phase 0: the Gaussian start;
+//   phase 1: one damped update from V (cumulative trapezoid in order);
+//   phase 2: psi from the final profile, in the storage type.
+// dynamic LDS (phase 1): n doubles.
 template <typename T>
 __global__ __launch_bounds__(kThreads) void haissinski_kernel(const SimDev *__restrict__ sims, int which, int buf,
-                                                              int iters, double alpha, int stage_lags)
+                                                              int phase, double alpha)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     __shared__ double red[kThreads];
     const SimDev &sd = sims[which];
     const int n = sd.n, tid = threadIdx.x;
-    double *rho = (double *)smem_raw, *V = rho + n, *F = V + n;
-    const double *wl = sd.wl64;
-    if (stage_lags && sd.has_wake) {
-        double *Wl = F + n;
-        for (int k = tid; k < 2 * n - 1; k += kThreads) Wl[k] = sd.wl64[k];
-        wl = Wl;
-    }
-    double part = 0.0;
-    for (int i = tid; i < n; i += kThreads) {
-        const double q = sd.q_min + i * sd.dq;
-        rho[i] = exp(-0.5 * q * q);
-        part += rho[i];
-    }
-    double tot = block_sum(part, red);
-    for (int i = tid; i < n; i += kThreads) rho[i] *= sd.Q0 / (sd.dq * tot);
-    __syncthreads();
-    for (int it = 0; it < iters; ++it) {
+    double *rho = sd.rho_out;
+    if (phase == 0) {
+        double part = 0.0;
         for (int i = tid; i < n; i += kThreads) {
-            // four interleaved partial sums over j keep several loads in flight
-            double v0 = 0.0, v1 = 0.0, v2 = 0.0, v3 = 0.0;
-            if (sd.has_wake) {
-                const double *wi = wl + i + n - 1;          // wi[-j] = w[i - j]
-                int j = 0;
-                for (; j + 3 < n; j += 4) {
-                    v0 = fma(wi[-j], rho[j], v0);
-                    v1 = fma(wi[-j - 1], rho[j + 1], v1);
-                    v2 = fma(wi[-j - 2], rho[j + 2], v2);
-                    v3 = fma(wi[-j - 3], rho[j + 3], v3);
-                }
-                for (; j < n; ++j) v0 = fma(wi[-j], rho[j], v0);
-            }
-            V[i] = sd.S * ((v0 + v1) + (v2 + v3));
+            const double q = sd.q_min + i * sd.dq;
+            part += exp(-0.5 * q * q);
         }
-        __syncthreads();
+        const double tot = block_sum(part, red);
+        for (int i = tid; i < n; i += kThreads) {
+            const double q = sd.q_min + i * sd.dq;
+            rho[i] = exp(-0.5 * q * q) * (sd.Q0 / (sd.dq * tot));
+        }
+    } else if (phase == 1) {
+        double *F = (double *)smem_raw;
+        const double *V = sd.v_out;
         if (tid == 0) {                      // cumulative trapezoid, in order
             double u = 0.0;
             F[0] = 0.0;
@@ -1089,28 +1074,28 @@ __global__ __launch_bounds__(kThreads) void haissinski_kernel(const SimDev *__re
             }
         }
         __syncthreads();
-        part = 0.0;
+        double part = 0.0;
         for (int i = tid; i < n; i += kThreads) {
             const double q = sd.q_min + i * sd.dq;
             F[i] = exp(-0.5 * q * q - F[i]);
             part += F[i];
         }
-        tot = block_sum(part, red);
+        const double tot = block_sum(part, red);
         for (int i = tid; i < n; i += kThreads) rho[i] = (1.0 - alpha) * rho[i] + alpha * F[i] * (sd.Q0 / (sd.dq * tot));
-        __syncthreads();
-    }
-    part = 0.0;
-    for (int j = tid; j < n; j += kThreads) {
-        const double p = sd.p_min + j * sd.dp;
-        part += exp(-0.5 * p * p);
-    }
-    const double G = block_sum(part, red);
-    T *out = (T *)sd.psi[buf];
-    for (int i = 0; i < n; ++i)
+    } else {
+        double part = 0.0;
         for (int j = tid; j < n; j += kThreads) {
             const double p = sd.p_min + j * sd.dp;
-            out[(size_t)i * n + j] = to_stored<T>(rho[i] * exp(-0.5 * p * p) / (sd.dp * G), sd.fixb);
+            part += exp(-0.5 * p * p);
         }
+        const double G = block_sum(part, red);
+        T *out = (T *)sd.psi[buf];
+        for (int i = blockIdx.x; i < n; i += gridDim.x)
+            for (int j = tid; j < n; j += kThreads) {
+                const double p = sd.p_min + j * sd.dp;
+                out[(size_t)i * n + j] = to_stored<T>(rho[i] * exp(-0.5 * p * p) / (sd.dp * G), sd.fixb);
+            }
+    }
 }
 
 // Q0 = dq * dp * sum psi0 of the FP64 input, before any conversion to the
