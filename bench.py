@@ -40,6 +40,15 @@ def workload(name):
     if name == "scan64":
         return inputs.config(4), "bf16", (
             "scan: 64 sims at 256^2, K=4, 1000 steps/period, S log-spaced 0.1-2.0, Pi in {0.5,1,2}")
+    if name == "single256":
+        return inputs.config(2), "fp32", (
+            "single simulation 256^2, K=4, 1000 steps/period, parallel-plate CSR Pi=1, S=0.3")
+    if name == "run512":
+        return inputs.config(3), "fp32", (
+            "single simulation 512^2, K=4, 2000 steps/period, parallel-plate CSR Pi=0.5, S=1.5")
+    if name == "equilibrium64":
+        return inputs.config(1), "fp64", (
+            "single simulation 64^2, K=3, 500 steps/period, zero current, FP64")
     raise SystemExit(f"unknown workload {name}")
 
 
@@ -134,7 +143,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=1000)
     ap.add_argument("--warmup", type=int, default=50)
-    ap.add_argument("--workload", default="scan200", choices=["scan200", "scan64"])
+    ap.add_argument("--workload", default="scan200",
+                    choices=["scan200", "scan64", "single256", "run512", "equilibrium64"])
     ap.add_argument("--precision", default=None, help="fp32 | bf16 | fp16 | fp64 (default: the workload's)")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu", action="store_true")
@@ -267,9 +277,13 @@ def main():
     # the device-side analysis and set-up calls of a scan, timed per call on the
     # host clock (synchronous calls: launch, device work and the copy of the result)
     aux = None
-    if not args.no_aux:
+    with_z = [s_ for s_ in sims if s_.Pi is not None and s_.z_scale != 0.0]
+    if not args.no_aux and with_z:
         import time as _time
-        big = [s_ for s_ in sims if s_.n == 1024][:2]
+        nmax = max(s_.n for s_ in with_z)
+        big = [s_ for s_ in with_z if s_.n == nmax][:2]
+        if len(big) == 1:
+            big = big * 2
         ab = vfp.Batch([vfp.sim_kwargs(s_, precision=prec) for s_ in big], stream=stream, torch_workspace=True)
         ab.step(5)
         torch.cuda.synchronize()
@@ -284,7 +298,7 @@ def main():
         n1 = big[0]
         aux = {
             "unit": "us per call (host clock, synchronous)",
-            "grid": "1024^2, padding 2",
+            "grid": f"{nmax}^2, padding {big[0].padding}",
             "impedance_samples_parallel_plates": per_call(
                 lambda: vfp.impedance_samples(n1.n, n1.padding, n1.q_min, n1.q_max, "parallel_plate", n1.Pi), 5),
             "csr_spectrum": per_call(lambda: ab.csr_spectrum(0), 10),
