@@ -323,17 +323,44 @@ int rebuild_units(vfp_batch *b)
             load[g] += (double)b->hs[s].p.n * b->hs[s].p.n;
         }
     }
+    // Units in dispatch order: block k*kXcds + x of a launch runs on XCD x (the
+    // dispatcher deals blocks round-robin).  Every XCD gets an equal share of
+    // each grid size's strips (contiguous runs of strips, so neighbouring
+    // strips of a simulation share their halo columns in that XCD's L2),
+    // larger grids first; the slot list is padded with empty units (w = 0)
+    // where an XCD's share is shorter than the longest.
+    constexpr int kXcds = 8;
     for (int g = 0; g < b->ngroups; ++g) {
-        b->unit_off[g] = b->units.size();
-        for (int s : b->active) {
-            if (group[s] != g) continue;
-            const int n = b->hs[s].p.n;
-            const int w = b->staged == 3 ? choose_strip_c(n, b->cells, b->rotation) : choose_strip(n, b->cells);
-            const int o0 = (b->K - 1) / 2;
-            const int SY = b->staged == 2 ? (n >= 256 ? 256 : (n + 63) / 64 * 64) + 2 * kH : kSY;
-            for (int i0 = 0; i0 < n; i0 += w)
-                b->units.push_back(Unit{s, i0, std::min(w, n - i0), (kH - o0) * (SY + 1)});
+        std::vector<int> sims_g;
+        for (int s : b->active)
+            if (group[s] == g) sims_g.push_back(s);
+        std::stable_sort(sims_g.begin(), sims_g.end(), [&](int x, int y) { return b->hs[x].p.n > b->hs[y].p.n; });
+        std::vector<std::vector<Unit>> xcd(kXcds);
+        for (size_t a = 0; a < sims_g.size();) {
+            const int n = b->hs[sims_g[a]].p.n;
+            std::vector<Unit> cls;               // strips of every simulation of this grid size
+            for (; a < sims_g.size() && b->hs[sims_g[a]].p.n == n; ++a) {
+                const int s = sims_g[a];
+                const int w = b->staged == 3 ? choose_strip_c(n, b->cells, b->rotation) : choose_strip(n, b->cells);
+                const int o0 = (b->K - 1) / 2;
+                const int SY = b->staged == 2 ? (n >= 256 ? 256 : (n + 63) / 64 * 64) + 2 * kH : kSY;
+                for (int i0 = 0; i0 < n; i0 += w)
+                    cls.push_back(Unit{s, i0, std::min(w, n - i0), (kH - o0) * (SY + 1)});
+            }
+            const size_t q = cls.size() / kXcds, r = cls.size() % kXcds;
+            size_t at = 0;
+            for (int x = 0; x < kXcds; ++x) {
+                const size_t len = q + ((size_t)x < r ? 1 : 0);
+                xcd[x].insert(xcd[x].end(), cls.begin() + at, cls.begin() + at + len);
+                at += len;
+            }
         }
+        size_t rounds = 0;
+        for (int x = 0; x < kXcds; ++x) rounds = std::max(rounds, xcd[x].size());
+        b->unit_off[g] = b->units.size();
+        for (size_t k = 0; k < rounds; ++k)
+            for (int x = 0; x < kXcds; ++x)
+                b->units.push_back(k < xcd[x].size() ? xcd[x][k] : Unit{0, 0, 0, 0});
         b->unit_cnt[g] = b->units.size() - b->unit_off[g];
     }
     if (b->units.size() > b->units_cap) {

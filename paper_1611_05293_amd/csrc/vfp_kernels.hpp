@@ -123,14 +123,9 @@ __device__ __forceinline__ double block_sum(double v, double *red)
     return t;
 }
 
-// unit index for this block: consecutive units (the strips of one
-// simulation) go to the same XCD, which the dispatcher picks round-robin
-__device__ __forceinline__ int xcd_unit(int b, int G)
-{
-    const int q = G >> 3, r = G & 7;
-    const int x = b & 7, k = b >> 3;
-    return x * q + (x < r ? x : r) + k;
-}
+// Work units of a step launch: the host lays them out in dispatch order
+// (block k*8 + x runs on XCD x), so block b takes units[b]; slots with
+// w == 0 are padding and their blocks return at once, before any barrier.
 
 // ----------------------------------------------- Lagrange weights (Sec. III.A)
 // FP64 closed forms of the basis over the offsets -1, 0, 1[, 2], with a
@@ -335,8 +330,8 @@ __global__ __launch_bounds__(kThreads) void step_kernel(const SimDev *__restrict
     __shared__ int sh_km[kMaxStrip];
     __shared__ double sh_s;
 
-    const int uidx = xcd_unit(blockIdx.x, nunits);
-    const Unit u = units[uidx];
+    const Unit u = units[blockIdx.x];
+    if (u.w == 0) return;                     // padding slot
     const SimDev &sd = sims[u.sim];
     const int n = sd.n, w = u.w, i0 = u.i0, tid = threadIdx.x;
     const T *__restrict__ src = (const T *)sd.psi[parity];

@@ -72,7 +72,8 @@ __global__ __launch_bounds__(kThreads) void step32_kernel(const SimDev *__restri
     __shared__ float sh_s;
     constexpr int o0 = (K - 1) / 2;
 
-    const Unit u = units[xcd_unit(blockIdx.x, nunits)];
+    const Unit u = units[blockIdx.x];
+    if (u.w == 0) return;                     // padding slot
     const SimDev &sd = sims[u.sim];
     const int n = sd.n, W = u.w, i0 = u.i0, tid = threadIdx.x, lane = tid & 63;
     const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);     // wave index, uniform

@@ -202,7 +202,8 @@ __global__ __launch_bounds__(kThreads) void step32c_kernel(const SimDev *__restr
     __shared__ float2 sh_xy[kMaxStripC];       // per column: ax0 + i*axi, cy0 + i*cyi
     constexpr int o0 = (K - 1) / 2;
 
-    const Unit u = units[xcd_unit(blockIdx.x, nunits)];
+    const Unit u = units[blockIdx.x];
+    if (u.w == 0) return;                     // padding slot
     const SimDev &sd = sims[u.sim];
     const int n = sd.n, W = u.w, i0 = u.i0, tid = threadIdx.x, lane = tid & 63;
     const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);

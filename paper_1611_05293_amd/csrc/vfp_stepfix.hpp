@@ -80,7 +80,8 @@ __global__ __launch_bounds__(kThreads) void stepfix_kernel(const SimDev *__restr
     __shared__ int sh_km[kMaxStrip];
     constexpr int o0 = (K - 1) / 2;
 
-    const Unit u = units[xcd_unit(blockIdx.x, nunits)];
+    const Unit u = units[blockIdx.x];
+    if (u.w == 0) return;                     // padding slot
     const SimDev &sd = sims[u.sim];
     const int n = sd.n, w = u.w, i0 = u.i0, tid = threadIdx.x, F = sd.fixb;
     const int64_t *__restrict__ src = (const int64_t *)sd.psi[parity];
