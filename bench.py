@@ -156,7 +156,7 @@ def main():
     ap.add_argument("--no-forms", action="store_true", help="skip the FP32 and Manhattan forms")
     ap.add_argument("--staged", type=int, default=None, help="FP32 step kernel layout: 0 generic, 1, 2, 3")
     ap.add_argument("--cells", type=int, default=0, help="cells per work unit (0: built-in)")
-    ap.add_argument("--streams", type=int, default=2, choices=[1, 2],
+    ap.add_argument("--streams", type=int, default=3, choices=[1, 2, 3, 4],
                     help="stream groups of the batch (1: every launch covers the whole batch, as in profiles)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 512 MiB device copy 5 times (scale of the HBM byte counters)")

@@ -242,14 +242,15 @@ int vfp_batch_get_raw(vfp_batch *b, int32_t i, void *out, double *s);
  * cell of LDS), graph replay and layout 3; 0 restores that default. */
 int vfp_batch_set_tuning(vfp_batch *b, int32_t cells_per_unit, int32_t use_graph, int32_t staged);
 
-/* Stream groups: with groups = 2 (the default) the active simulations are
- * split in two halves of about equal cell count, each advanced on its own
- * stream (the second one is created by the library, default priority), so
- * that the wake of one half overlaps the step of the other; the two streams
- * are joined before every record and at the end of every call.  groups = 1
- * advances all simulations on the batch's stream.  Results are identical
- * either way.  Per-kernel timing (vfp_batch_kernel_timing) uses one group.
- * Returns VFP_EINVAL for other values. */
+/* Stream groups: with groups = 2, 3 (the default) or 4 the active
+ * simulations are split in that many parts of about equal cell count (never
+ * more parts than simulations), each advanced on its own stream (the others
+ * are created by the library, default priority), so that the wake of one
+ * part overlaps the steps of the others; the streams are joined before every
+ * record and at the end of every call.  groups = 1 advances all simulations
+ * on the batch's stream.  Results are identical either way.  Per-kernel
+ * timing (vfp_batch_kernel_timing) uses one group.  Returns VFP_EINVAL for
+ * groups outside [1, 4]. */
 int vfp_batch_set_streams(vfp_batch *b, int32_t groups);
 
 /* The tuning in force: cells per unit, graph replay on/off, kernel layout

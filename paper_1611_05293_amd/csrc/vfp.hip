@@ -57,6 +57,8 @@ void lds_limit(K kernel, size_t bytes, int &cur)
             cur = (int)bytes;
     }
 }
+constexpr int kMaxGroups = 4;   // stream groups of a batch
+
 size_t align_up(size_t x) { return (x + kAlign - 1) & ~(kAlign - 1); }
 
 struct HostSim {
@@ -260,14 +262,16 @@ struct vfp_batch {
     std::vector<WakeTile> wtiles;
     WakeTile *d_wtiles = nullptr;
     size_t wtiles_cap = 0;
-    // stream groups: the active simulations split in two halves (by cells), each
-    // advanced on its own stream so that one half's wake overlaps the other's step
-    int lanes = 2;                 // tuning: 1 or 2 groups
+    // stream groups: the active simulations split in up to kMaxGroups parts of
+    // about equal cell count, each advanced on its own stream so that one part's
+    // wake overlaps the others' steps
+    int lanes = 3;                 // tuning: groups requested (1 .. kMaxGroups)
     int ngroups = 1;               // groups in use (1 for a single simulation or while timing)
-    size_t unit_off[2] = {0, 0}, unit_cnt[2] = {0, 0}, tile_off[2] = {0, 0}, tile_cnt[2] = {0, 0};
-    hipStream_t stream2 = nullptr;
-    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+    size_t unit_off[kMaxGroups] = {}, unit_cnt[kMaxGroups] = {}, tile_off[kMaxGroups] = {}, tile_cnt[kMaxGroups] = {};
+    hipStream_t xstream[kMaxGroups - 1] = {};   // streams of groups 1 .. kMaxGroups-1
+    hipEvent_t ev_fork = nullptr, ev_join[kMaxGroups - 1] = {};
     bool forked = false;
+    int forked_groups = 0;         // groups forked by the last fork_streams
     // launch target of the group being launched
     const Unit *cur_units = nullptr;
     int cur_nunits = 0;
@@ -311,14 +315,17 @@ int rebuild_units(vfp_batch *b)
         if (b->hs[s].active) b->active.push_back(s);
     b->units.clear();
     // groups: balance the cells of the active simulations over the streams
-    b->ngroups = (b->lanes == 2 && b->active.size() >= 2 && !b->timing) ? 2 : 1;
+    // (largest grids first, each to the group with the fewest cells so far)
+    b->ngroups = b->timing ? 1 : std::max(1, std::min(b->lanes, (int)b->active.size()));
     std::vector<int> group(b->count, 0);
-    if (b->ngroups == 2) {
+    if (b->ngroups > 1) {
         std::vector<int> order(b->active);
         std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return b->hs[x].p.n > b->hs[y].p.n; });
-        double load[2] = {0.0, 0.0};
+        double load[kMaxGroups] = {};
         for (int s : order) {
-            const int g = load[1] < load[0] ? 1 : 0;
+            int g = 0;
+            for (int h = 1; h < b->ngroups; ++h)
+                if (load[h] < load[g]) g = h;
             group[s] = g;
             load[g] += (double)b->hs[s].p.n * b->hs[s].p.n;
         }
@@ -575,25 +582,28 @@ void select_group(vfp_batch *b, int g)
     b->cur_nunits = (int)b->unit_cnt[g];
     b->cur_tiles = b->d_wtiles ? b->d_wtiles + b->tile_off[g] : nullptr;
     b->cur_ntiles = (int)b->tile_cnt[g];
-    b->cur_stream = g == 0 ? b->stream : b->stream2;
+    b->cur_stream = g == 0 ? b->stream : b->xstream[g - 1];
 }
 
-// the second stream starts after the work already queued on the batch's stream
+// the other groups' streams start after the work already queued on the batch's stream
 int fork_streams(vfp_batch *b)
 {
     if (b->ngroups < 2 || b->forked) return VFP_OK;
     HIPCHK(hipEventRecord(b->ev_fork, b->stream));
-    HIPCHK(hipStreamWaitEvent(b->stream2, b->ev_fork, 0));
+    for (int g = 1; g < b->ngroups; ++g) HIPCHK(hipStreamWaitEvent(b->xstream[g - 1], b->ev_fork, 0));
     b->forked = true;
+    b->forked_groups = b->ngroups;
     return VFP_OK;
 }
 
-// the batch's stream continues after the second stream's work
+// the batch's stream continues after the other groups' work
 int join_streams(vfp_batch *b)
 {
     if (!b->forked) return VFP_OK;
-    HIPCHK(hipEventRecord(b->ev_join, b->stream2));
-    HIPCHK(hipStreamWaitEvent(b->stream, b->ev_join, 0));
+    for (int g = 1; g < b->forked_groups; ++g) {
+        HIPCHK(hipEventRecord(b->ev_join[g - 1], b->xstream[g - 1]));
+        HIPCHK(hipStreamWaitEvent(b->stream, b->ev_join[g - 1], 0));
+    }
     b->forked = false;
     return VFP_OK;
 }
@@ -798,12 +808,14 @@ void free_batch(vfp_batch *b)
     if (b->d_ring_rows) (void)hipFree(b->d_ring_rows);
     if (b->d_stage) (void)hipFree(b->d_stage);
     for (hipEvent_t e : b->ev_pool) (void)hipEventDestroy(e);
-    if (b->stream2) {
-        (void)hipStreamSynchronize(b->stream2);
-        (void)hipStreamDestroy(b->stream2);
+    for (int g = 0; g < kMaxGroups - 1; ++g) {
+        if (b->xstream[g]) {
+            (void)hipStreamSynchronize(b->xstream[g]);
+            (void)hipStreamDestroy(b->xstream[g]);
+        }
+        if (b->ev_join[g]) (void)hipEventDestroy(b->ev_join[g]);
     }
     if (b->ev_fork) (void)hipEventDestroy(b->ev_fork);
-    if (b->ev_join) (void)hipEventDestroy(b->ev_join);
     if (b->own_stream) (void)hipStreamDestroy(b->stream);
     delete b;
 }
@@ -958,9 +970,11 @@ int create_impl(const vfp_params *p, int32_t count, void *stream, void *ws, size
         }
         b->own_stream = true;
     }
-    if (hipStreamCreateWithFlags(&b->stream2, hipStreamNonBlocking) != hipSuccess ||
-        hipEventCreateWithFlags(&b->ev_fork, hipEventDisableTiming) != hipSuccess ||
-        hipEventCreateWithFlags(&b->ev_join, hipEventDisableTiming) != hipSuccess) {
+    bool made = hipEventCreateWithFlags(&b->ev_fork, hipEventDisableTiming) == hipSuccess;
+    for (int g = 0; g < kMaxGroups - 1 && made; ++g)
+        made = hipStreamCreateWithFlags(&b->xstream[g], hipStreamNonBlocking) == hipSuccess &&
+               hipEventCreateWithFlags(&b->ev_join[g], hipEventDisableTiming) == hipSuccess;
+    if (!made) {
         free_batch(b);
         return fail(VFP_EDEVICE, "stream creation failed");
     }
@@ -1477,7 +1491,7 @@ extern "C" int vfp_batch_debug_vout(vfp_batch *b, int32_t i, double *out)
 
 int vfp_batch_set_streams(vfp_batch *b, int32_t groups)
 {
-    if (!b || (groups != 1 && groups != 2)) return fail(VFP_EINVAL, "groups must be 1 or 2");
+    if (!b || groups < 1 || groups > kMaxGroups) return fail(VFP_EINVAL, "groups must be in [1, 4]");
     HIPCHK(hipStreamSynchronize(b->stream));
     b->lanes = groups;
     b->units_dirty = true;

@@ -284,7 +284,8 @@ class Batch:
         _check(load().vfp_batch_set_tuning(self._h, int(cells_per_unit), int(bool(use_graph)), int(staged)))
 
     def set_streams(self, groups: int):
-        """1: every simulation on the batch's stream; 2: two halves on two streams."""
+        """1: every simulation on the batch's stream; 2-4: that many parts of
+        about equal cell count, each on its own stream."""
         _check(load().vfp_batch_set_streams(self._h, int(groups)))
 
     def get_tuning(self) -> tuple:

@@ -213,12 +213,13 @@ def test_strong_kick_every_read_path(staged):
 
 
 @pytest.mark.parametrize("precision", ["fp16", "fp32"])
-def test_two_stream_groups_equal_one(precision):
-    """The two-stream split of a batch gives bit-identical states and records
-    to advancing every simulation on one stream (graph replay and direct)."""
+def test_stream_groups_equal_one(precision):
+    """Splitting a batch over two, three or four streams gives bit-identical
+    states and records to advancing every simulation on one stream (graph
+    replay and direct)."""
     sims = mixed_sims()
     out = []
-    for groups, graph in ((1, True), (2, True), (2, False)):
+    for groups, graph in ((1, True), (2, True), (2, False), (3, True), (4, True), (4, False)):
         b = vfp.Batch([vfp.sim_kwargs(s, precision=precision) for s in sims])
         b.set_tuning(0, graph, 3)
         b.set_streams(groups)
