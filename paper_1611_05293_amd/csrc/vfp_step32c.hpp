@@ -16,9 +16,11 @@
 //     lane) and walks over the columns, so the four stencil coefficients of
 //     each row (with the renormalisation factor s and the zero rows outside
 //     the grid folded in) are formed once per block instead of per cell.
-// Chunks are CH = 192 rows for every grid size; a staged column holds
-// rows j0-4 .. j0+CH+3, so every 16-byte load is aligned (n % 4 == 0), and
-// its fixed length keeps all tap offsets compile-time immediates.
+// Chunks are CH = 256 rows for every grid size (whole chunks on the
+// power-of-two grids); a staged column holds rows j0-4 .. j0+CH+3, so every
+// 16-byte load is aligned (n % 4 == 0), and its fixed length keeps all tap
+// offsets compile-time immediates.  Its 66 quads are one per lane plus eight
+// rows that travel one per lane in a shared prefetch register.
 // LDS: A[W][n + 2*kPad], S[W + 2*kH][CH + 8] and, for the Manhattan
 // rotation, Dm[W][CH + 8].
 #pragma once
@@ -26,7 +28,7 @@
 namespace vfp {
 
 #ifndef VFP_CH
-#define VFP_CH 192
+#define VFP_CH 256
 #endif
 constexpr int kCH = VFP_CH;       // rows per chunk (a multiple of 64)
 constexpr int kSYC = kCH + 8;     // staged rows per column: j0-4 .. j0+kCH+3
@@ -297,10 +299,16 @@ __global__ __launch_bounds__(kThreads) void step32c_kernel(const SimDev *__restr
 
     // ---- phase R: chunks of CH rows
     // staged column x is source column i0 - kH + x; its LDS row y is row j0 - 4 + y;
-    // lane l moves rows j0 - 4 + 4l .. +3 (lanes l < Q4)
+    // lane l moves rows j0 - 4 + 4l .. +3 (lanes l < Q4).  A staged column of
+    // more than 64 quads (CH > 248) has DX = 4 (Q4 - 64) rows beyond the
+    // lanes' quads (rows j0 + 252 ..); those of prefetched column k are one
+    // row per lane in lanes DX k .. DX k + DX-1 of a single register.
+    constexpr int DX = Q4 > 64 ? 4 * (Q4 - 64) : 0;
+    static_assert(DX * kPF4 <= 64, "the extra rows of every prefetched column fit one register");
     const int ncolw = (SX - wv + kWaves - 1) / kWaves;
     const bool lane_ld = lane < Q4;
     u32x4 pf[kPF4];
+    unsigned pfx = 0;
     auto load_cols = [&](int j0, int cw0) {
         // rows above the grid (first chunk, lane 0) get an offset far past the
         // column instead of a negative one, so the 16-byte range check cannot wrap
@@ -314,6 +322,13 @@ __global__ __launch_bounds__(kThreads) void step32c_kernel(const SimDev *__restr
                 const __amdgpu_buffer_rsrc_t r = column_rsrc(src + (size_t)(ok ? gi : 0) * n, ok ? n : 0);
                 pf[k] = __builtin_amdgcn_raw_buffer_load_b128(r, voff, 0, 0);
             }
+            if constexpr (DX > 0) {
+                if (cw0 + k < ncolw && lane / DX == k) {
+                    const bool ok = gi >= 0 && gi < n;
+                    const __amdgpu_buffer_rsrc_t r = column_rsrc(src + (size_t)(ok ? gi : 0) * n, ok ? n : 0);
+                    pfx = __builtin_amdgcn_raw_buffer_load_b32(r, (j0 + 252 + lane % DX) * 4, 0, 0);
+                }
+            }
         }
     };
     auto store_cols = [&](int cw0) {
@@ -321,6 +336,11 @@ __global__ __launch_bounds__(kThreads) void step32c_kernel(const SimDev *__restr
         for (int k = 0; k < kPF4; ++k) {
             const int x = wv + kWaves * (cw0 + k);
             if (cw0 + k < ncolw && lane_ld) *(u32x4 *)(S + x * SY + 4 * lane) = pf[k];
+        }
+        if constexpr (DX > 0) {
+            const int k = lane / DX;
+            if (k < kPF4 && cw0 + k < ncolw)
+                *(unsigned *)(S + (wv + kWaves * (cw0 + k)) * SY + 256 + lane % DX) = pfx;
         }
     };
     load_cols(0, 0);
