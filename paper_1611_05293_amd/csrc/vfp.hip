@@ -83,7 +83,7 @@ int choose_strip(int n, int cells)
 
 // Strip width of the chunked staged layout: at most kMaxStripC columns, the
 // per-(column, 256-row block, lane) partial sums fit the staging buffer
-// (W * nb * 64 <= (W + 2*kH) * kSYC floats), and a grid with more than one
+// (W * nb * 64 <= (W + 2*kH) * staged_rows_c floats), and a grid with more than one
 // chunk keeps every staged column of a wave in the prefetch registers.
 // The dynamic LDS of a unit stays under kLdsBudgetC so that five workgroups
 // fit on a compute unit.
@@ -93,14 +93,15 @@ int choose_strip(int n, int cells)
 constexpr size_t kLdsBudgetC = VFP_LDS_BUDGET;
 size_t lds_bytes_c(int n, int w, int rotation)
 {
-    return ((size_t)w * (n + 2 * kPad) + (size_t)(w + 2 * kH) * kSYC + (rotation ? (size_t)w * kSYC : 0)) * 4;
+    const size_t sy = staged_rows_c(rotation);
+    return ((size_t)w * (n + 2 * kPad) + (size_t)(w + 2 * kH) * sy + (rotation ? (size_t)w * sy : 0)) * 4;
 }
 int choose_strip_c(int n, int cells, int rotation)
 {
     int w = std::max(1, std::min(cells / n, std::min(n, kMaxStripC)));
     const int nb = (n + 255) / 256;
-    while (w > 1 && (size_t)w * nb * 64 > (size_t)(w + 2 * kH) * kSYC) --w;
-    if (n > kCH) w = std::min(w, kWaves * kPF4 - 2 * kH);
+    while (w > 1 && (size_t)w * nb * 64 > (size_t)(w + 2 * kH) * staged_rows_c(rotation)) --w;
+    if (n > chunk_rows_c(rotation)) w = std::min(w, kWaves * kPF4 - 2 * kH);
     while (w > 1 && lds_bytes_c(n, w, rotation) > kLdsBudgetC) --w;
     return std::max(w, 1);
 }

@@ -17,21 +17,22 @@
 //     each row (with the renormalisation factor s and the zero rows outside
 //     the grid folded in) are formed once per block instead of per cell.
 // Chunks are CH = 256 rows for every grid size (whole chunks on the
-// power-of-two grids); a staged column holds rows j0-4 .. j0+CH+3, so every
-// 16-byte load is aligned (n % 4 == 0), and its fixed length keeps all tap
-// offsets compile-time immediates.  Its 66 quads are one per lane plus eight
-// rows that travel one per lane in a shared prefetch register.
+// power-of-two grids; 192 with the Manhattan rotation); a staged column holds
+// rows j0-4 .. j0+CH+3, so every 16-byte load is aligned (n % 4 == 0), and
+// its fixed length keeps all tap offsets compile-time immediates.  Its 66
+// quads (CH = 256) are one per lane plus eight rows that travel one per lane
+// in a shared prefetch register.
 // LDS: A[W][n + 2*kPad], S[W + 2*kH][CH + 8] and, for the Manhattan
 // rotation, Dm[W][CH + 8].
 #pragma once
 
 namespace vfp {
 
-#ifndef VFP_CH
-#define VFP_CH 256
-#endif
-constexpr int kCH = VFP_CH;       // rows per chunk (a multiple of 64)
-constexpr int kSYC = kCH + 8;     // staged rows per column: j0-4 .. j0+kCH+3
+// rows per chunk (a multiple of 64): 256 for the standard rotation, 192 for
+// the Manhattan rotation, whose drifted rows take a third buffer of the
+// chunk's length; a staged column holds rows j0-4 .. j0+CH+3
+__host__ __device__ constexpr int chunk_rows_c(int rot) { return rot == 1 ? 192 : 256; }
+__host__ __device__ constexpr int staged_rows_c(int rot) { return chunk_rows_c(rot) + 8; }
 constexpr int kPF4 = 4;           // staged columns per wave held in registers across a chunk
 constexpr int kMaxStripC = 64;    // columns per work unit in this layout
 
@@ -210,7 +211,7 @@ __global__ __launch_bounds__(kThreads) void step32c_kernel(const SimDev *__restr
     const int n = sd.n, W = u.w, i0 = u.i0, tid = threadIdx.x, lane = tid & 63;
     const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int LA = n + 2 * kPad;
-    constexpr int CH = kCH, SY = kSYC, Q4 = SY / 4;
+    constexpr int CH = chunk_rows_c(ROT), SY = staged_rows_c(ROT), Q4 = SY / 4;
     const int SX = W + 2 * kH;
     float *A = (float *)smem_raw;
     float *S = A + (size_t)W * LA;
@@ -362,7 +363,7 @@ __global__ __launch_bounds__(kThreads) void step32c_kernel(const SimDev *__restr
                 const int cb4 = (int)lds_addr(S + (c + kH - o0) * SY + lane + 4 - o0);
                 float *acol = A + c * LA + kPad + j0 + lane;
 #pragma unroll
-                for (int rb = 0; rb < kCH; rb += 64) {
+                for (int rb = 0; rb < CH; rb += 64) {
                     if (j0 + rb >= n) break;
                     const int j = j0 + rb + lane;
                     if (j < n) {
@@ -406,7 +407,7 @@ __global__ __launch_bounds__(kThreads) void step32c_kernel(const SimDev *__restr
                 const float *col = Dm + c * SY + lane + 4 + sh_rm[c] - o0;
                 float *acol = A + c * LA + kPad + j0 + lane;
 #pragma unroll
-                for (int rb = 0; rb < kCH; rb += 64) {
+                for (int rb = 0; rb < CH; rb += 64) {
                     if (j0 + rb >= n) break;
                     if (j0 + rb + lane < n) {
                         float f[K];
