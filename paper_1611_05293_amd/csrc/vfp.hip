@@ -344,6 +344,7 @@ int rebuild_units(vfp_batch *b)
             if (group[s] == g) sims_g.push_back(s);
         std::stable_sort(sims_g.begin(), sims_g.end(), [&](int x, int y) { return b->hs[x].p.n > b->hs[y].p.n; });
         std::vector<std::vector<Unit>> xcd(kXcds);
+        int x0 = 0;                              // next XCD to take a remainder strip
         for (size_t a = 0; a < sims_g.size();) {
             const int n = b->hs[sims_g[a]].p.n;
             std::vector<Unit> cls;               // strips of every simulation of this grid size
@@ -355,13 +356,16 @@ int rebuild_units(vfp_batch *b)
                 for (int i0 = 0; i0 < n; i0 += w)
                     cls.push_back(Unit{s, i0, std::min(w, n - i0), (kH - o0) * (SY + 1)});
             }
+            // q strips to every XCD and one more to r of them, taken in turn
+            // across the grid sizes so that the remainders do not pile up
             const size_t q = cls.size() / kXcds, r = cls.size() % kXcds;
             size_t at = 0;
             for (int x = 0; x < kXcds; ++x) {
-                const size_t len = q + ((size_t)x < r ? 1 : 0);
+                const size_t len = q + ((size_t)((x - x0 + kXcds) % kXcds) < r ? 1 : 0);
                 xcd[x].insert(xcd[x].end(), cls.begin() + at, cls.begin() + at + len);
                 at += len;
             }
+            x0 = (int)((x0 + r) % kXcds);
         }
         size_t rounds = 0;
         for (int x = 0; x < kXcds; ++x) rounds = std::max(rounds, xcd[x].size());
