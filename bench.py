@@ -145,7 +145,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=50)
     ap.add_argument("--workload", default="scan200",
                     choices=["scan200", "scan64", "single256", "run512", "equilibrium64"])
-    ap.add_argument("--precision", default=None, help="fp32 | bf16 | fp16 | fp64 (default: the workload's)")
+    ap.add_argument("--precision", default=None,
+                    help="fp32 | bf16 | fp16 | fp64 | fixed (44 fractional bits) (default: the workload's)")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-parity", action="store_true")
@@ -196,7 +197,7 @@ def main():
     sims, prec, desc = workload(args.workload)
     prec = args.precision or prec
     cells_tick = sum(s.n * s.n for s in sims)
-    es = 8 if prec == "fp64" else 4
+    es = 8 if prec in ("fp64", "fixed") else 4     # bytes per stored cell (fixed point: int64)
     log(f"workload {args.workload}: {len(sims)} sims, {cells_tick} cells per tick, precision {prec}")
     stream = torch.cuda.Stream()
     with torch.cuda.stream(stream):
@@ -334,11 +335,11 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64" if prec == "fp64" else "f32",
+        "dtype": {"fp64": "f64", "fixed": "int64"}.get(prec, "f32"),
         "data": "synthetic",
         "config": {"workload": desc, "form": "batched, one fused launch per tick from a hipGraph",
                    "wake": {"fp16": "FP16 hi/lo MFMA", "bf16": "BF16 hi/lo MFMA",
-                            "fp32": "FP32 VALU", "fp64": "FP64 VALU"}[prec],
+                            "fp32": "FP32 VALU", "fp64": "FP64 VALU", "fixed": "FP64 VALU"}[prec],
                    "sims": len(sims), "cells_per_tick": cells_tick,
                    "cells_per_unit": cells_unit, "kernel_layout": args.staged, "stream_groups": args.streams},
         "parity": None if err is None else {"max_rel_l1_vs_fp64_oracle": err, "after_steps": args.warmup,
