@@ -212,6 +212,26 @@ def test_strong_kick_every_read_path(staged):
         assert err <= 1e-5, (i, err)
 
 
+def test_stream_group_count_is_validated():
+    """Group counts outside [1, 4] are rejected with VFP_EINVAL; more groups
+    than simulations run as one group per simulation."""
+    sims = mixed_sims()[:2]
+    b = vfp.Batch([vfp.sim_kwargs(s, precision="fp32") for s in sims])
+    for bad in (0, 5, -1):
+        with pytest.raises(vfp.VfpError) as e:
+            b.set_streams(bad)
+        assert e.value.code == vfp.VFP_EINVAL
+    b.set_streams(4)                 # two simulations: two groups
+    b.step(3)
+    ref = vfp.Batch([vfp.sim_kwargs(s, precision="fp32") for s in sims])
+    ref.set_streams(1)
+    ref.step(3)
+    for i in range(len(sims)):
+        assert np.array_equal(b.get_psi(i), ref.get_psi(i))
+    b.close()
+    ref.close()
+
+
 @pytest.mark.parametrize("precision", ["fp16", "fp32"])
 def test_stream_groups_equal_one(precision):
     """Splitting a batch over two, three or four streams gives bit-identical
