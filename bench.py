@@ -52,10 +52,22 @@ def workload(name):
     raise SystemExit(f"unknown workload {name}")
 
 
+def _cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "host CPU"
+
+
 def cpu_baseline(sims, seconds):
     """The FP64 oracle on this host's cores over a bounded sample of the same
-    workload: the simulations picked in the workload's size ratio, advanced
-    tick by tick (OpenMP over columns inside each simulation)."""
+    workload: one simulation per 20 of each grid size (the workload's size
+    ratio), advanced over a prefix of ticks one simulation after another with
+    the oracle's OpenMP loops over columns.  Timed twice: with all the
+    threads OpenMP gives the process and with one thread."""
     import oracle
     by_n = {}
     for i, s in enumerate(sims):
@@ -73,28 +85,36 @@ def cpu_baseline(sims, seconds):
         d = (s.q_max - s.q_min) / (s.n - 1) * (s.p_max - s.p_min) / (s.n - 1)
         prep.append((p, w, psi, d * psi.sum(), s.n))
     cells_tick = sum(x[4] ** 2 for x in prep)
-    t0 = time.perf_counter()
-    for p, w, psi, Q0, _ in prep:
-        oracle.run(p, w, psi, 1, Q0)
-    one = time.perf_counter() - t0
-    ticks = max(1, int(seconds / max(one, 1e-6)))
-    t0 = time.perf_counter()
-    for p, w, psi, Q0, _ in prep:
-        oracle.run(p, w, psi, ticks, Q0)
-    dt = time.perf_counter() - t0
-    model = ""
+
+    def rate(budget):
+        t0 = time.perf_counter()
+        for p, w, psi, Q0, _ in prep:
+            oracle.run(p, w, psi, 1, Q0)
+        one = time.perf_counter() - t0
+        ticks = max(1, int(budget / max(one, 1e-6)))
+        t0 = time.perf_counter()
+        for p, w, psi, Q0, _ in prep:
+            oracle.run(p, w, psi, ticks, Q0)
+        dt = time.perf_counter() - t0
+        return cells_tick * ticks / dt, ticks, dt
+
+    threads = oracle.threads()
+    v_all, t_all, dt_all = rate(0.6 * seconds)
+    oracle.set_threads(1)
     try:
-        for line in open("/proc/cpuinfo"):
-            if line.startswith("model name"):
-                model = line.split(":", 1)[1].strip()
-                break
-    except OSError:
-        pass
+        v_one, t_one, dt_one = rate(0.4 * seconds)
+    finally:
+        oracle.set_threads(threads)
+    try:
+        affinity = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        affinity = os.cpu_count()
     return {
-        "value": cells_tick * ticks / dt, "unit": "cell-updates/s", "cores": oracle.threads(),
-        "kind": "oracle",
-        "sample": f"{len(pick)} sims ({'+'.join(f'{counts[n]}x{n}^2' for n in ns)}) x {ticks} steps, FP64, "
-                  f"{dt:.1f} s on {model or 'host CPU'}",
+        "value": v_all, "unit": "cell-updates/s", "cores": threads, "kind": "oracle",
+        "value_1core": v_one, "nproc": os.cpu_count(), "cpus_allowed": affinity, "cpu_model": _cpu_model(),
+        "sample": f"{len(pick)} sims ({'+'.join(f'{counts[n]}x{n}^2' for n in ns)}), a prefix of {t_all} ticks "
+                  f"({dt_all:.1f} s) on {threads} OpenMP threads (loops over columns) and {t_one} ticks "
+                  f"({dt_one:.1f} s) on 1 thread, FP64",
     }
 
 
@@ -315,7 +335,8 @@ def main():
     if not args.no_cpu:
         log("timing the oracle on the host")
         cpu = cpu_baseline(sims, args.cpu_seconds)
-        log(f"oracle: {cpu['value']:.3e} cell-updates/s on {cpu['cores']} threads")
+        log(f"oracle: {cpu['value']:.3e} cell-updates/s on {cpu['cores']} threads, {cpu['value_1core']:.3e} on 1 "
+            f"({cpu['cpu_model']}, nproc {cpu['nproc']})")
 
     # HBM bytes per launch from the stored counter summary, only while it was
     # taken on the current kernel sources (and only for the workload it covers)
@@ -337,7 +358,8 @@ def main():
         "vs_baseline": None,
         "dtype": {"fp64": "f64", "fixed": "int64"}.get(prec, "f32"),
         "data": "synthetic",
-        "config": {"workload": desc, "form": "batched, one fused launch per tick from a hipGraph",
+        "config": {"workload": desc, "form": (f"batched; a tick is, in each of {args.streams} stream groups, one wake launch then one fused "
+                            f"step launch (FP64 forms: the step launch alone), replayed from hipGraphs"),
                    "wake": {"fp16": "FP16 hi/lo MFMA", "bf16": "BF16 hi/lo MFMA",
                             "fp32": "FP32 VALU", "fp64": "FP64 VALU", "fixed": "FP64 VALU"}[prec],
                    "sims": len(sims), "cells_per_tick": cells_tick,

@@ -82,6 +82,7 @@ def load():
         lib = C.CDLL(_LIB)
         P = C.POINTER(_P)
         lib.vfo_threads.restype = C.c_int
+        lib.vfo_set_threads.argtypes = [C.c_int]
         lib.vfo_lagrange_weights.argtypes = [C.c_int, C.c_double, _dp]
         lib.vfo_profile.argtypes = [P, _dp, _dp]
         lib.vfo_charge.argtypes = [P, _dp]
@@ -126,6 +127,11 @@ def _ptr(x):
 
 def threads() -> int:
     return int(load().vfo_threads())
+
+
+def set_threads(t: int) -> None:
+    """Thread count of the oracle's OpenMP loops (for 1-core vs all-core timing)."""
+    load().vfo_set_threads(int(t))
 
 
 def lagrange_weights(K: int, t: float) -> np.ndarray:

@@ -45,6 +45,16 @@ int vfo_threads(void)
 #endif
 }
 
+/* set the thread count of the parallel loops (timing on 1 core vs all) */
+void vfo_set_threads(int t)
+{
+#ifdef _OPENMP
+    if (t > 0) omp_set_num_threads(t);
+#else
+    (void)t;
+#endif
+}
+
 typedef struct {
     int    n;                 /* grid points per axis                          */
     double q_min, q_max;      /* node range in q                               */

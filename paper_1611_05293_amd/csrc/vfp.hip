@@ -1485,15 +1485,6 @@ int vfp_batch_set_tuning(vfp_batch *b, int32_t cells_per_unit, int32_t use_graph
     return VFP_OK;
 }
 
-#ifdef VFP_WAKE_PROBE
-extern "C" int vfp_batch_debug_vout(vfp_batch *b, int32_t i, double *out)
-{
-    HIPCHK(hipStreamSynchronize(b->stream));
-    HIPCHK(hipMemcpy(out, b->sd[i].v_out, sizeof(double) * b->hs[i].p.n, hipMemcpyDeviceToHost));
-    return VFP_OK;
-}
-#endif
-
 int vfp_batch_set_streams(vfp_batch *b, int32_t groups)
 {
     if (!b || groups < 1 || groups > kMaxGroups) return fail(VFP_EINVAL, "groups must be in [1, 4]");
@@ -1674,17 +1665,25 @@ int vfp_batch_autotune(vfp_batch *b, int32_t ticks, int32_t *chosen_cells, int32
     int rc = VFP_OK;
     for (int layout : layouts) {
         for (int c : cand) {
+            // every stream group has drained the previous candidate's ticks before its
+            // unit and tile arrays are rewritten
+            rc = join_streams(b);
+            if (rc == VFP_OK && hipStreamSynchronize(b->stream) != hipSuccess) rc = fail(VFP_EDEVICE, "autotune sync failed");
+            if (rc) break;
             b->cells = c;
             b->staged = layout;
             b->units_dirty = true;
             rc = rebuild_units(b);
             if (rc == VFP_EINVAL) { rc = VFP_OK; continue; }   // does not fit the LDS
             if (rc) break;
-            // warm up, then time
+            // warm up, then time; the end event waits for every group's ticks
             for (int t = 0; t < 2 && rc == VFP_OK; ++t) { rc = launch_tick(b, b->parity); b->parity ^= 1; }
+            if (rc == VFP_OK) rc = join_streams(b);
             if (rc) break;
             HIPCHK(hipEventRecord(e0, b->stream));
             for (int t = 0; t < ticks && rc == VFP_OK; ++t) { rc = launch_tick(b, b->parity); b->parity ^= 1; }
+            if (rc == VFP_OK) rc = join_streams(b);
+            if (rc) break;
             HIPCHK(hipEventRecord(e1, b->stream));
             HIPCHK(hipEventSynchronize(e1));
             float ms = 0.0f;
@@ -1695,16 +1694,28 @@ int vfp_batch_autotune(vfp_batch *b, int32_t ticks, int32_t *chosen_cells, int32
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
-    // restore
+    // restore, after every group's trial ticks have finished (stream-ordered copies)
+    {
+        const int jrc = join_streams(b);
+        if (rc == VFP_OK) rc = jrc;
+    }
+    b->forked = false;
+    HIPCHK(hipStreamSynchronize(b->stream));
+    for (int g = 0; g < kMaxGroups - 1; ++g)
+        if (b->xstream[g]) HIPCHK(hipStreamSynchronize(b->xstream[g]));
     for (int s = 0; s < b->count; ++s) {
         const HostSim &h = b->hs[s];
         const size_t nn = (size_t)h.p.n * h.p.n;
-        HIPCHK(hipMemcpy(b->arena + h.off_psi[0], save[s].data(), nn * es, hipMemcpyHostToDevice));
-        HIPCHK(hipMemcpy(b->arena + h.off_psi[1], save[s].data() + nn * es, nn * es, hipMemcpyHostToDevice));
         const size_t cb = cs_bytes(b->precision, h.p.n);
-        HIPCHK(hipMemcpy(b->arena + h.off_cs[0], save[s].data() + 2 * nn * es, cb, hipMemcpyHostToDevice));
-        HIPCHK(hipMemcpy(b->arena + h.off_cs[1], save[s].data() + 2 * nn * es + cb, cb, hipMemcpyHostToDevice));
+        HIPCHK(hipMemcpyAsync(b->arena + h.off_psi[0], save[s].data(), nn * es, hipMemcpyHostToDevice, b->stream));
+        HIPCHK(hipMemcpyAsync(b->arena + h.off_psi[1], save[s].data() + nn * es, nn * es, hipMemcpyHostToDevice,
+                              b->stream));
+        HIPCHK(hipMemcpyAsync(b->arena + h.off_cs[0], save[s].data() + 2 * nn * es, cb, hipMemcpyHostToDevice,
+                              b->stream));
+        HIPCHK(hipMemcpyAsync(b->arena + h.off_cs[1], save[s].data() + 2 * nn * es + cb, cb, hipMemcpyHostToDevice,
+                              b->stream));
     }
+    HIPCHK(hipStreamSynchronize(b->stream));
     b->tick = tick0;
     b->parity = parity0;
     b->every = every0;

@@ -801,15 +801,6 @@ __global__ void wake_split_kernel(int n, const double *__restrict__ wl64, double
 
 constexpr int kWakePer = 16;      // column sums per thread held in registers: n <= 4096
 
-#ifdef VFP_WAKE_PROBE
-#define VFP_WAKE_MARK(k)                                                                      \
-    do {                                                                                      \
-        if (tid == 0) sd.v_out[8 * wt.tile + (k)] = (double)wall_clock64();                   \
-    } while (0)
-#else
-#define VFP_WAKE_MARK(k) do { } while (0)
-#endif
-
 template <bool FP16>
 __global__ __launch_bounds__(kThreads) void wake_mfma2_kernel(const SimDev *__restrict__ sims,
                                                               const WakeTile *__restrict__ tiles, int parity)
@@ -834,7 +825,6 @@ __global__ __launch_bounds__(kThreads) void wake_mfma2_kernel(const SimDev *__re
     typedef const __attribute__((address_space(1))) double gdouble;
     typedef const __attribute__((address_space(1))) uint16_t gu16;
     gdouble *cs = (gdouble *)sd.colsum[parity];
-    VFP_WAKE_MARK(0);
 
     // column sums: each thread loads its share once (n <= kWakePer * kThreads);
     // issued first so their latency overlaps the lag staging below
@@ -857,7 +847,6 @@ __global__ __launch_bounds__(kThreads) void wake_mfma2_kernel(const SimDev *__re
             *(v4u *)(c0h + (size_t)arr * NLp + 8 * q) = v;
         }
     }
-    VFP_WAKE_MARK(1);
     // rho entries outside the grid are zero
     for (int k = tid; k < NR; k += kThreads) {
         const int g = 16 * Jlo + k;
@@ -876,7 +865,6 @@ __global__ __launch_bounds__(kThreads) void wake_mfma2_kernel(const SimDev *__re
     part = red[0];
     mx = red[kWaves];
     for (int k = 1; k < kWaves; ++k) { part += red[k]; mx = fmax(mx, red[kWaves + k]); }
-    VFP_WAKE_MARK(2);
     const double Qh = part * sd.dq * sd.dp;
     const double s = sd.renorm ? sd.Q0 / Qh : 1.0;
     const double rmax = mx * s * sd.dp;
@@ -894,7 +882,6 @@ __global__ __launch_bounds__(kThreads) void wake_mfma2_kernel(const SimDev *__re
         }
     }
     __syncthreads();
-    VFP_WAKE_MARK(3);
 
     const int a = lane & 15, kq = 4 * (lane >> 4);
     // y0 = Lhi - (16d + a - kq) for d = dmax is 15 - a + kq; even y0 read copy 0 at y0,
@@ -930,7 +917,6 @@ __global__ __launch_bounds__(kThreads) void wake_mfma2_kernel(const SimDev *__re
         }
         A_h = nA_h; A_l = nA_l; B_h = nB_h; B_l = nB_l;
     }
-    VFP_WAKE_MARK(4);
     double t[4];
     for (int q = 0; q < 4; ++q) t[q] = (double)acc0[q] + ((double)acc1[q] + (double)acc2[q]);
     if (wv > 0)
@@ -946,7 +932,6 @@ __global__ __launch_bounds__(kThreads) void wake_mfma2_kernel(const SimDev *__re
         }
         if (wt.tile == 0 && lane == 0) sd.sext[0] = s;
     }
-    VFP_WAKE_MARK(5);
 }
 
 // Vector-ALU wake of the FP32 form, one workgroup per (simulation, tile of
