@@ -9,7 +9,7 @@ integer sums for the fixed-point form; ``-O2 -ffp-contract=off``); this
 module only builds and marshals.
 """
 from .oracle import (  # noqa: F401
-    OracleParams, build, load, threads, lagrange_weights, wake_kernel, profile, charge,
+    OracleParams, build, load, threads, set_threads, lagrange_weights, wake_kernel, profile, charge,
     wake, rotate, rotate_manhattan, kick, fokker_planck, moments, csr_power, csr_spectrum,
     step, run, run_many, haissinski, fix_quantize, fix_charge, fix_step, fix_run,
 )
