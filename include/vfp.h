@@ -146,6 +146,21 @@ void vfp_params_init(vfp_params *p);
 int vfp_impedance_samples(int32_t model, int32_t n, int32_t padding, double q_min, double q_max,
                           double Pi, double *z_re, double *z_im);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * samples as vfp_impedance_samples, bit for bit, with the device buffer taken
+ * from a static array of the library instead of hipMalloc.  Each GPU the
+ * library runs on holds its own copy of that array (2 * VFP_NOALLOC_MAX_SAMPLES
+ * doubles, 256 KiB) until the process ends; its device address is looked up
+ * on the first call on each device.  Arguments, layout and ownership as
+ * vfp_impedance_samples; additionally returns VFP_EINVAL when
+ * padding*n/2 + 1 > VFP_NOALLOC_MAX_SAMPLES.  Calls no hipMalloc/hipFree.
+ * Every call on one GPU shares that GPU's array: calls that overlap on one
+ * GPU (from several host threads) race and must be serialised by the caller. */
+#define VFP_NOALLOC_MAX_SAMPLES 16385
+int vfp_impedance_samples_noalloc(int32_t model, int32_t n, int32_t padding, double q_min,
+                                  double q_max, double Pi, double *z_re, double *z_im);
+
 /* sizeof(vfp_params) as compiled into the library (binding layout check). */
 size_t vfp_params_sizeof(void);
 

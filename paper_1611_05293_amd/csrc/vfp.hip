@@ -15,6 +15,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -27,6 +28,10 @@
 #include "vfp_stepfix.hpp"
 
 using namespace vfp;
+
+// Device scratch of vfp_impedance_samples_noalloc: Re and Im of at most
+// VFP_NOALLOC_MAX_SAMPLES impedance samples (256 KiB).
+static __device__ __align__(256) double scratch[2 * VFP_NOALLOC_MAX_SAMPLES];
 
 namespace {
 
@@ -1260,6 +1265,60 @@ int read_record_impl(vfp_batch *b, int s, double *out, int64_t *rows)
     return VFP_OK;
 }
 
+// ----------------------------------------------------- impedance sampling
+int impedance_args(int32_t model, int32_t n, int32_t padding, double q_min, double q_max, double Pi,
+                   const double *z_re, const double *z_im)
+{
+    if (model != VFP_Z_PARALLEL_PLATES && model != VFP_Z_FREE_SPACE) return fail(VFP_EINVAL, "unknown impedance model");
+    if (n < 16 || n > 4096 || padding < 2 || (int64_t)padding * n > (1 << 24))
+        return fail(VFP_EINVAL, "need n in [16, 4096] and padding >= 2");
+    if (!(q_max > q_min) || !std::isfinite(q_min) || !std::isfinite(q_max))
+        return fail(VFP_EINVAL, "need finite q_min < q_max");
+    if (model == VFP_Z_PARALLEL_PLATES && !(Pi > 0.0 && std::isfinite(Pi)))
+        return fail(VFP_EINVAL, "Pi must be finite and > 0");
+    if (!z_re || !z_im) return fail(VFP_EINVAL, "z_re and z_im are required");
+    return VFP_OK;
+}
+
+// Samples into the device buffer d (2*(M/2+1) doubles: Re then Im) on the
+// null stream, then copied to the host arrays; true on success.
+bool impedance_on_device(int32_t model, int32_t n, int32_t padding, double q_min, double q_max, double Pi, double *d,
+                         double *z_re, double *z_im)
+{
+    const int M = padding * n, nz = M / 2 + 1;
+    const double dq = (q_max - q_min) / (n - 1);
+    hipLaunchKernelGGL(impedance_kernel, dim3((nz + kThreads - 1) / kThreads), dim3(kThreads), 0, nullptr, nz,
+                       2.0 * M_PI / (M * dq), model, std::pow(Pi, 2.0 / 3.0), d, d + nz);
+    return hipGetLastError() == hipSuccess &&
+           hipMemcpy(z_re, d, nz * sizeof(double), hipMemcpyDeviceToHost) == hipSuccess &&
+           hipMemcpy(z_im, d + nz, nz * sizeof(double), hipMemcpyDeviceToHost) == hipSuccess;
+}
+
+// Static scratch of the allocation-free sampler: every device the library
+// runs on holds one copy until the process ends.  Host code never passes the
+// symbol itself to a kernel or copy (on the host it only names the variable);
+// it uses the device address that hipGetSymbolAddress returns for the
+// current device, looked up once per device.
+constexpr int kScratchDevices = 64;
+std::mutex g_scratch_mu;
+double *g_scratch_ptr[kScratchDevices] = {};
+
+int scratch_on_current_device(double **out)
+{
+    int dev = -1;
+    HIPCHK(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kScratchDevices) return fail(VFP_EDEVICE, "device index beyond the scratch table");
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *ptr = nullptr;
+        HIPCHK(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+        if (!ptr) return fail(VFP_EDEVICE, "no device address for the static scratch");
+        g_scratch_ptr[dev] = (double *)ptr;
+    }
+    *out = g_scratch_ptr[dev];
+    return VFP_OK;
+}
+
 }  // namespace
 
 // ====================================================================== ABI
@@ -1292,25 +1351,31 @@ size_t vfp_params_sizeof(void) { return sizeof(vfp_params); }
 int vfp_impedance_samples(int32_t model, int32_t n, int32_t padding, double q_min, double q_max, double Pi,
                           double *z_re, double *z_im)
 {
-    if (model != VFP_Z_PARALLEL_PLATES && model != VFP_Z_FREE_SPACE) return fail(VFP_EINVAL, "unknown impedance model");
-    if (n < 16 || n > 4096 || padding < 2 || (int64_t)padding * n > (1 << 24))
-        return fail(VFP_EINVAL, "need n in [16, 4096] and padding >= 2");
-    if (!(q_max > q_min) || !std::isfinite(q_min) || !std::isfinite(q_max))
-        return fail(VFP_EINVAL, "need finite q_min < q_max");
-    if (model == VFP_Z_PARALLEL_PLATES && !(Pi > 0.0 && std::isfinite(Pi)))
-        return fail(VFP_EINVAL, "Pi must be finite and > 0");
-    if (!z_re || !z_im) return fail(VFP_EINVAL, "z_re and z_im are required");
-    const int M = padding * n, nz = M / 2 + 1;
-    const double dq = (q_max - q_min) / (n - 1);
+    const int rc = impedance_args(model, n, padding, q_min, q_max, Pi, z_re, z_im);
+    if (rc) return rc;
+    const int nz = padding * n / 2 + 1;
     double *d = nullptr;
     HIPCHK(hipMalloc(&d, 2 * (size_t)nz * sizeof(double)));
-    hipLaunchKernelGGL(impedance_kernel, dim3((nz + kThreads - 1) / kThreads), dim3(kThreads), 0, nullptr, nz,
-                       2.0 * M_PI / (M * dq), model, std::pow(Pi, 2.0 / 3.0), d, d + nz);
-    const bool ok = hipGetLastError() == hipSuccess &&
-                    hipMemcpy(z_re, d, nz * sizeof(double), hipMemcpyDeviceToHost) == hipSuccess &&
-                    hipMemcpy(z_im, d + nz, nz * sizeof(double), hipMemcpyDeviceToHost) == hipSuccess;
+    const bool ok = impedance_on_device(model, n, padding, q_min, q_max, Pi, d, z_re, z_im);
     (void)hipFree(d);
     return ok ? VFP_OK : fail(VFP_EDEVICE, "impedance evaluation failed");
+}
+
+int vfp_impedance_samples_noalloc(int32_t model, int32_t n, int32_t padding, double q_min, double q_max, double Pi,
+                                  double *z_re, double *z_im)
+{
+    const int rc = impedance_args(model, n, padding, q_min, q_max, Pi, z_re, z_im);
+    if (rc) return rc;
+    const int nz = padding * n / 2 + 1;
+    if (nz > VFP_NOALLOC_MAX_SAMPLES)
+        return fail(VFP_EINVAL, "padding*n/2 + 1 = " + std::to_string(nz) + " samples exceed the static scratch of " +
+                                    std::to_string(VFP_NOALLOC_MAX_SAMPLES) + " (use vfp_impedance_samples)");
+    double *d = nullptr;
+    const int rs = scratch_on_current_device(&d);
+    if (rs) return rs;
+    return impedance_on_device(model, n, padding, q_min, q_max, Pi, d, z_re, z_im)
+               ? VFP_OK
+               : fail(VFP_EDEVICE, "impedance evaluation failed");
 }
 
 const char *vfp_last_error(void) { return g_err.c_str(); }

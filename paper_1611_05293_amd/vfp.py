@@ -74,6 +74,8 @@ def load():
             "vfp_params_sizeof": (C.c_size_t, []),
             "vfp_impedance_samples": (C.c_int, [C.c_int32, C.c_int32, C.c_int32, C.c_double, C.c_double,
                                                 C.c_double, _dp, _dp]),
+            "vfp_impedance_samples_noalloc": (C.c_int, [C.c_int32, C.c_int32, C.c_int32, C.c_double, C.c_double,
+                                                        C.c_double, _dp, _dp]),
             "vfp_workspace_size": (C.c_int, [P, C.c_int32, C.POINTER(C.c_size_t)]),
             "vfp_create": (C.c_int, [P, h, h, C.c_size_t, C.POINTER(h)]),
             "vfp_step": (C.c_int, [h, C.c_int64]),
@@ -175,16 +177,17 @@ def make_params(n=256, q_range=(-8.0, 8.0), p_range=None, steps_per_period=1000,
     return p, (zr, zi, ps)
 
 
-def impedance_samples(n, padding, q_min, q_max, model="parallel_plate", Pi=1.0):
+def impedance_samples(n, padding, q_min, q_max, model="parallel_plate", Pi=1.0, noalloc=False):
     """Z_k at kappa_k = 2 pi k / (M dq), k = 0..M/2, evaluated on the device
     (the samples a simulation created with z_model=model uses).  Returns
-    (z_re, z_im) as float64 arrays."""
+    (z_re, z_im) as float64 arrays.  noalloc=True calls the entry point that
+    uses the library's static device scratch instead of allocating."""
     M = int(padding) * int(n)
     zr = np.empty(M // 2 + 1, dtype=np.float64)
     zi = np.empty(M // 2 + 1, dtype=np.float64)
     m = Z_MODELS[model] if isinstance(model, str) else int(model)
-    _check(load().vfp_impedance_samples(m, int(n), int(padding), float(q_min), float(q_max), float(Pi),
-                                        _ptr(zr), _ptr(zi)))
+    fn = load().vfp_impedance_samples_noalloc if noalloc else load().vfp_impedance_samples
+    _check(fn(m, int(n), int(padding), float(q_min), float(q_max), float(Pi), _ptr(zr), _ptr(zi)))
     return zr, zi
 
 
