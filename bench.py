@@ -21,8 +21,9 @@ sys.path.insert(0, ROOT)
 
 METRIC = "phase-space cell-updates/s (N²·steps·sims/s), batched vs plain, at stated L1 err"
 HBM_PEAK_GBS = 8000.0
-# step kernel of each layout (0: generic kernel, also the FP64 path)
-STEP_KERNEL = {0: "vfp::step_kernel", 1: "vfp::step32_kernel", 2: "vfp::step32b_kernel", 3: "vfp::step32c_kernel"}
+# the kernel of a tick: 1 the fused one-launch tick of the FP32-storage forms
+# (LDS-staged step plus the next wake), 0 the generic step kernel (also FP64)
+STEP_KERNEL = {0: "vfp::step_kernel", 1: "vfp::tick32_kernel"}
 TRAFFIC_FILE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles",
                             "step_kernel_hbm_traffic_scan200_fp16.json")
 
@@ -135,7 +136,8 @@ def parity(b, sims, idxs, nsteps):
 
 
 def timed(b, stream, cells_tick, es, steps):
-    """K ticks from the graph between events on the batch's stream, then the
+    """K ticks between events on the batch's stream (graph replays prepared at
+    create, single launches for a remainder shorter than a graph), then the
     per-kernel averages from a pass with events around every launch."""
     import torch
     e0 = torch.cuda.Event(enable_timing=True)
@@ -175,16 +177,14 @@ def main():
     ap.add_argument("--plain-steps", type=int, default=20)
     ap.add_argument("--autotune", action="store_true")
     ap.add_argument("--no-forms", action="store_true", help="skip the FP32 and Manhattan forms")
-    ap.add_argument("--staged", type=int, default=None, help="FP32 step kernel layout: 0 generic, 1, 2, 3")
+    ap.add_argument("--staged", type=int, default=None, help="FP32 step kernel: 0 generic, 1 staged (fused tick)")
     ap.add_argument("--cells", type=int, default=0, help="cells per work unit (0: built-in)")
-    ap.add_argument("--streams", type=int, default=3, choices=[1, 2, 3, 4],
-                    help="stream groups of the batch (1: every launch covers the whole batch, as in profiles)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 512 MiB device copy 5 times (scale of the HBM byte counters)")
     ap.add_argument("--counter-summary", nargs=4, metavar=("FETCH", "WRITE", "COPY_FETCH", "COPY_WRITE"),
                     help="write the step kernel's HBM bytes per launch from four rocprofv3 --pmc output "
                          "folders (no GPU needed) and exit")
-    ap.add_argument("--layout-for-summary", type=int, default=3)
+    ap.add_argument("--layout-for-summary", type=int, default=1)
     args = ap.parse_args()
     if args.counter_summary:
         from paper_1611_05293_amd import inputs, profiles
@@ -229,7 +229,6 @@ def main():
     if args.autotune:
         tuned, layout = b.autotune(ticks=10)
         log(f"autotuned: {tuned} cells per unit, kernel layout {layout}")
-    b.set_streams(args.streams)
     cells_unit, _, args.staged = b.get_tuning()
     b.step(args.warmup)
     torch.cuda.synchronize()
@@ -261,8 +260,7 @@ def main():
             fsteps = min(args.steps, 50) if wide else args.steps
             fb = vfp.Batch([vfp.sim_kwargs(s_, precision=fprec, rotation=rot, **extra) for s_ in sims],
                            stream=stream, torch_workspace=True)
-            fb.set_tuning(0 if wide else cells_unit, True, args.staged)
-            fb.set_streams(args.streams)
+            fb.set_tuning(0 if wide else cells_unit, True, 0 if wide else args.staged)
             fb.step(min(args.warmup, 5 if wide else 20))
             fr = timed(fb, stream, cells_tick, 8 if wide else 4, fsteps)
             forms[name] = {"value": fr["value"], "ms_per_step": fr["ms"] / fsteps, "steps": fsteps,
@@ -358,12 +356,17 @@ def main():
         "vs_baseline": None,
         "dtype": {"fp64": "f64", "fixed": "int64"}.get(prec, "f32"),
         "data": "synthetic",
-        "config": {"workload": desc, "form": (f"batched; a tick is, in each of {args.streams} stream groups, one wake launch then one fused "
-                            f"step launch (FP64 forms: the step launch alone), replayed from hipGraphs"),
+        "config": {"workload": desc,
+                   "form": ("batched; a tick is one launch (each work unit steps its strip; the last unit of "
+                            "each simulation computes its next wake), replayed from hipGraphs of 16 ticks"
+                            if args.staged == 1 and prec not in ("fp64", "fixed") else
+                            "batched; a tick is one step launch with the wake slice inside, replayed from hipGraphs"
+                            if prec in ("fp64", "fixed") else
+                            "batched; a tick is a wake launch then a step launch (generic kernel), from hipGraphs"),
                    "wake": {"fp16": "FP16 hi/lo MFMA", "bf16": "BF16 hi/lo MFMA",
                             "fp32": "FP32 VALU", "fp64": "FP64 VALU", "fixed": "FP64 VALU"}[prec],
                    "sims": len(sims), "cells_per_tick": cells_tick,
-                   "cells_per_unit": cells_unit, "kernel_layout": args.staged, "stream_groups": args.streams},
+                   "cells_per_unit": cells_unit, "kernel_layout": args.staged},
         "parity": None if err is None else {"max_rel_l1_vs_fp64_oracle": err, "after_steps": args.warmup,
                                             "sims_checked": "one per grid size"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",

@@ -35,8 +35,14 @@
  * own.  The stream is the caller's hipStream_t; with NULL the handle creates
  * a non-blocking stream of its own (graphs cannot be captured on the null
  * stream).
- * Stepping calls only enqueue work on that stream; the query calls
- * (profile, csr_power, moments, get_psi, read_record) synchronise it.
+ * Stepping calls (vfp_step, vfp_batch_step) only enqueue work on that
+ * stream: they never allocate, never synchronise and never capture or
+ * instantiate a graph.  The work layout of every retirement phase and the
+ * graphs are prepared by create and by the calls that change the set of
+ * simulations, their state or the tuning (set_psi, seed, haissinski, record,
+ * set_tuning, kernel_timing, autotune), which may allocate and synchronise.
+ * The query calls (profile, csr_power, moments, get_psi, read_record)
+ * synchronise the stream.
  *
  * Errors: every int-returning call returns one of the VFP_* codes and never
  * aborts; vfp_last_error() returns a thread-local description of the last
@@ -215,9 +221,19 @@ const char *vfp_last_error(void);
 /* ---------------------------------------------------------------------- */
 /* Batched form: `count` independent simulations (a current or shielding   */
 /* scan; grid sizes and steps per period may differ) advanced together.    */
-/* One tick advances every active simulation by one of its own steps with  */
-/* one fused launch (two in the mixed modes: the matrix-core wake first),  */
-/* replayed from a captured hipGraph.  All simulations of a batch share    */
+/* One tick advances every active simulation by one of its own steps.  The */
+/* FP32-storage forms (VFP_FP32 and the mixed forms) run one of two tick   */
+/* forms (vfp_batch_set_tuning): split, a wake launch then the fused step  */
+/* launch; or fused, ONE launch in which every work unit steps its strip   */
+/* with the wake the previous tick left and wake tiles placed after the    */
+/* units compute each simulation's next wake once its units are done (the */
+/* first tick after a state change is preceded by one wake launch).        */
+/* VFP_FP64 and VFP_FIXED compute the wake slice of each strip inside      */
+/* their one step launch.  The simulations are split in stream groups     */
+/* (vfp_batch_set_streams) whose launches overlap.  Ticks are replayed     */
+/* from hipGraphs prepared outside the step call.  A simulation with       */
+/* max_steps > 0 retires after that many steps; retirements switch between */
+/* work layouts prepared in advance.  All simulations of a batch share     */
 /* interp, clamp, precision and rotation.                                  */
 /* ---------------------------------------------------------------------- */
 int vfp_batch_create(const vfp_params *p, int32_t count, void *hip_stream, void *workspace,
@@ -246,26 +262,29 @@ int vfp_batch_get_raw(vfp_batch *b, int32_t i, void *out, double *s);
 /* Launch tuning: columns per work unit are chosen per grid size.  cells is
  * the number of phase-space cells one workgroup owns (0 restores the
  * built-in choice); use_graph = 0 launches every tick directly; staged
- * selects the FP32 step kernel where a staged one applies: 0 the generic
- * kernel, 1 the staged kernel with 64-row chunks and separate kick and
- * damping passes, 2 the staged kernel with 256-row chunks and the kick merged
- * into the damping pass, 3 the staged kernel with 192-row chunks, 16-byte
- * staging, FP32 source displacements and per-row damping coefficients
- * (same arithmetic definition, different evaluation order; returns
- * VFP_EINVAL for other values).  A new batch uses cells_per_unit 8192
+ * selects the FP32-storage step kernel and tick form: 0 the generic kernel
+ * (taps through the caches; the wake in a launch of its own), 1 the
+ * LDS-staged kernel with a separate wake launch per tick (split), 2 the
+ * LDS-staged kernel with the one-launch tick (fused).  The three give the
+ * same arithmetic definition with different evaluation orders; 1 and 2 give
+ * bit-identical results.  Other values return VFP_EINVAL.  Grids the staged
+ * kernel does not take (n % 4 != 0, rotation source more than 2 cells away)
+ * use the generic kernel either way.  A new batch uses cells_per_unit 8192
  * (1024 for VFP_FP64 and 2048 for VFP_FIXED, whose strips take 16 bytes per
- * cell of LDS), graph replay and layout 3; 0 restores that default. */
+ * cell of LDS), graph replay and staged = 1; 0 restores the default cells.
+ * Synchronises the stream and prepares the work layout. */
 int vfp_batch_set_tuning(vfp_batch *b, int32_t cells_per_unit, int32_t use_graph, int32_t staged);
 
 /* Stream groups: with groups = 2, 3 (the default) or 4 the active
  * simulations are split in that many parts of about equal cell count (never
  * more parts than simulations), each advanced on its own stream (the others
- * are created by the library, default priority), so that the wake of one
- * part overlaps the steps of the others; the streams are joined before every
- * record and at the end of every call.  groups = 1 advances all simulations
- * on the batch's stream.  Results are identical either way.  Per-kernel
- * timing (vfp_batch_kernel_timing) uses one group.  Returns VFP_EINVAL for
- * groups outside [1, 4]. */
+ * are created by the library, default priority), so that the launches of one
+ * part overlap the others' and the tail of each launch is filled; the
+ * streams are joined before every record and at the end of every step call.
+ * groups = 1 advances all simulations on the batch's stream.  Results are
+ * identical either way.  Per-kernel timing (vfp_batch_kernel_timing) uses
+ * one group.  Returns VFP_EINVAL for groups outside [1, 4]; synchronises the
+ * stream and prepares the work layout. */
 int vfp_batch_set_streams(vfp_batch *b, int32_t groups);
 
 /* The tuning in force: cells per unit, graph replay on/off, kernel layout
@@ -304,19 +323,22 @@ int vfp_batch_seed(vfp_batch *b, int32_t dst, int32_t src);
 int vfp_batch_last_wake(vfp_batch *b, int32_t i, double *V);
 
 /* Per-kernel timing with HIP events on the handle's stream: while enabled,
- * ticks are launched directly (not from a graph) and every launch of the
- * fused step kernel and of the matrix-core wake kernel is bracketed by a pair
- * of events.  Enabling (or disabling) clears the accumulated events.
+ * ticks are launched directly (not from a graph) and every step launch (the
+ * fused tick) and every separate wake launch is bracketed by a pair of
+ * events, from a pool of 3072 events made when timing is enabled (launches
+ * beyond the pool run untimed).  Enabling (or disabling) clears the
+ * accumulated events.
  * vfp_batch_kernel_times synchronises and returns
  * out = {step kernel total ms, step launches, wake kernel total ms, wake launches}. */
 int vfp_batch_kernel_timing(vfp_batch *b, int32_t enable);
 int vfp_batch_kernel_times(vfp_batch *b, double out[4]);
 
 /* Autotuner: times `ticks` ticks for every candidate (cells per unit in
- * {2048, 4096, 8192, 16384}, {1024, 2048, 4096, 8192} for the 8-byte forms,
- * and, for FP32 storage, the staged layouts 1, 2 and 3) with HIP events on
- * the batch's stream, keeps the fastest and returns it.  The state is saved
- * and restored around the trials. */
+ * {2048, 4096, 8192, 16384} and, for FP32 storage, the split and fused tick
+ * forms; {1024, 2048, 4096, 8192} with the generic kernel for the 8-byte
+ * forms) with HIP events on the batch's stream in the batch's stream groups,
+ * keeps the fastest and returns it.  The state is saved and restored around
+ * the trials. */
 int vfp_batch_autotune(vfp_batch *b, int32_t ticks, int32_t *chosen_cells, int32_t *chosen_staged);
 
 /* Architecture name of the current device (e.g. "gfx950:sramecc+:xnack-"),

@@ -21,8 +21,6 @@
 
 #include "vfp.h"
 #include "vfp_kernels.hpp"
-#include "vfp_step32.hpp"
-#include "vfp_step32b.hpp"
 #include "vfp_step32c.hpp"
 #include "vfp_impedance.hpp"
 #include "vfp_stepfix.hpp"
@@ -62,7 +60,13 @@ void lds_limit(K kernel, size_t bytes, int &cur)
             cur = (int)bytes;
     }
 }
-constexpr int kMaxGroups = 4;   // stream groups of a batch
+constexpr int kMaxGraphPhases = 8;   // retirement phases that get graphs
+constexpr int kMaxGroups = 4;        // stream groups of a batch
+constexpr int kXcds = 8;             // XCDs of the GPU: the dispatcher deals blocks to them round-robin
+// tuning values of `staged`: the generic kernel, the LDS-staged kernel with a
+// separate wake launch per tick, the LDS-staged kernel with the one-launch tick
+constexpr int kStagedGeneric = 0, kStagedSplit = 1, kStagedFused = 2;
+constexpr int kTimingEvents = 3 * 1024;   // event pool of the kernel timing mode
 
 size_t align_up(size_t x) { return (x + kAlign - 1) & ~(kAlign - 1); }
 
@@ -210,8 +214,8 @@ size_t layout(const vfp_params *p, int count, std::vector<HostSim> *hs)
         h.off_wl32 = off; off = align_up(off + (2 * n - 1) * 4);
         h.off_frag = off;
         if (is_mixed(q.precision)) off = align_up(off + (size_t)4 * wake_rev_len(q.n) * sizeof(uint16_t));
-        h.off_vext = off; off = align_up(off + n * 4);
-        h.off_sext = off; off = align_up(off + 2 * 8);
+        h.off_vext = off; off = align_up(off + 2 * n * 4);
+        h.off_sext = off; off = align_up(off + 3 * 8);
         h.off_rho = off; off = align_up(off + n * 8);
         h.off_v = off; off = align_up(off + n * 8);
         h.off_stat = off; off = align_up(off + 8 * 8);
@@ -222,6 +226,34 @@ size_t layout(const vfp_params *p, int count, std::vector<HostSim> *hs)
 }
 
 }  // namespace
+
+// One stream's share of a phase: its units (and wake tiles, and for the fused
+// tick the interleaved item list) in the shared device arrays.
+struct Group {
+    size_t unit_off = 0, unit_cnt = 0, tile_off = 0, tile_cnt = 0, item_off = 0, item_cnt = 0;
+    size_t act_off = 0, act_cnt = 0;                 // the group's simulations, into d_active
+    hipGraph_t graph[2] = {nullptr, nullptr};        // G ticks of this group starting at parity 0 / 1
+    hipGraphExec_t gexec[2] = {nullptr, nullptr};
+};
+
+// Work of one retirement phase: the simulations active between two
+// retirements (absolute ticks [start, end)), split in stream groups, each
+// with graphs of G ticks starting at either parity (one stream per graph: a
+// graph holds no dependency on another stream).  Built outside the step call
+// (create and every call that changes the set, the state or the tuning), so
+// that stepping only selects among them.
+struct Phase {
+    int64_t start = 0, end = INT64_MAX;
+    std::vector<int> active;        // active simulations
+    std::vector<int> retire;        // simulations whose budget ends at `end`
+    int ngroups = 1;
+    Group grp[kMaxGroups];
+    bool fast = false;              // every active simulation takes the staged FP32 kernel
+    bool wake = false;              // some active simulation has an impedance
+    size_t lds_step = 0;            // dynamic LDS of the step launch (fused tick: with the wake)
+    size_t lds_wake = 0;            // dynamic LDS of a separate wake launch
+    bool graphs = false;            // every group has its graphs
+};
 
 struct vfp_batch {
     int count = 0;
@@ -235,25 +267,34 @@ struct vfp_batch {
     unsigned char *arena = nullptr;
     size_t arena_bytes = 0;
     bool own_arena = false;
-    // units of the active simulations
-    int cells = 0;
-    std::vector<Unit> units;
-    Unit *d_units = nullptr;
-    size_t units_cap = 0;
-    std::vector<int> active;       // active simulation indices
-    int *d_active = nullptr;       // device copy of `active`
+    int cells = 0;                 // tuning: cells per work unit
+    int staged = kStagedSplit;     // tuning: kernel and tick form (kStaged*)
+    bool use_graph = true;         // tuning: replay ticks from hipGraphs
+    int lanes = 3;                 // tuning: stream groups requested (1 .. kMaxGroups)
+    // retirement phases; all phases' units, items, active lists and wake tiles on the device
+    std::vector<Phase> phases;
+    int cur = 0;                   // current phase
+    int G = 16;                    // ticks per graph replay
+    std::vector<Unit> units, items;
+    std::vector<int> actv;
+    std::vector<WakeTile> wtiles;
+    Unit *d_units = nullptr, *d_items = nullptr;
+    int *d_active = nullptr;
+    WakeTile *d_wtiles = nullptr;
+    size_t units_cap = 0, items_cap = 0, actv_cap = 0, wtiles_cap = 0;
+    unsigned *d_done = nullptr;    // fused tick: [2][count] finished units per simulation and tick parity
+    int *d_flag = nullptr;         // fused tick: set when a wake tile's wait exceeded its bound
+    bool wake_valid = false;       // vext/sext[parity] hold the wake of every active simulation's current state
     int *d_idx = nullptr;          // scratch index arrays for per-call kernels (2*count)
     int *d_buf01 = nullptr;        // count zeros then count ones: buffer tables for records
-    bool units_dirty = true;
     int64_t tick = 0;              // ticks since create
     int parity = 0;                // buffer holding the state of active simulations
-    // graph
-    bool use_graph = true;
-    hipGraphExec_t gexec = nullptr;
-    hipGraph_t graph = nullptr;
-    int graph_ticks = 0, graph_parity = -1;
-    int64_t graph_phase = -1;
-    bool graph_valid = false;
+    // stream groups: group 0 runs on the batch's stream, groups 1.. on streams of
+    // the library (default priority), forked from and joined into the batch's stream
+    hipStream_t xstream[kMaxGroups - 1] = {};
+    hipEvent_t ev_fork = nullptr, ev_join[kMaxGroups - 1] = {};
+    bool forked = false;
+    int forked_groups = 0;
     // record
     int every = 0;
     int64_t rec_cap = 0, rec_base = 0;
@@ -262,31 +303,12 @@ struct vfp_batch {
     // staging for psi transfers and impedance uploads
     double *d_stage = nullptr;
     size_t stage_elems = 0;
-    size_t lds_step = 0, lds_stats = 0, lds_wake = 0;
-    bool fast = false;             // all active simulations use the FP32 staged kernel
-    int staged = 3;                // tuning: 0 generic kernel, 1, 2, 3 the staged FP32 layouts
-    std::vector<WakeTile> wtiles;
-    WakeTile *d_wtiles = nullptr;
-    size_t wtiles_cap = 0;
-    // stream groups: the active simulations split in up to kMaxGroups parts of
-    // about equal cell count, each advanced on its own stream so that one part's
-    // wake overlaps the others' steps
-    int lanes = 3;                 // tuning: groups requested (1 .. kMaxGroups)
-    int ngroups = 1;               // groups in use (1 for a single simulation or while timing)
-    size_t unit_off[kMaxGroups] = {}, unit_cnt[kMaxGroups] = {}, tile_off[kMaxGroups] = {}, tile_cnt[kMaxGroups] = {};
-    hipStream_t xstream[kMaxGroups - 1] = {};   // streams of groups 1 .. kMaxGroups-1
-    hipEvent_t ev_fork = nullptr, ev_join[kMaxGroups - 1] = {};
-    bool forked = false;
-    int forked_groups = 0;         // groups forked by the last fork_streams
-    // launch target of the group being launched
-    const Unit *cur_units = nullptr;
-    int cur_nunits = 0;
-    const WakeTile *cur_tiles = nullptr;
-    int cur_ntiles = 0;
-    hipStream_t cur_stream = nullptr;
-    // per-kernel event timing (direct launches while enabled)
+    size_t lds_stats = 0;
+    // per-kernel event timing (direct launches in one group while enabled); the
+    // events are made when timing is switched on, never inside a step call
     bool timing = false;
     std::vector<hipEvent_t> ev_pool;
+    size_t ev_used = 0;
     std::vector<std::pair<int, int>> ev_step, ev_wake;   // (start, stop) indices into ev_pool
 };
 
@@ -314,295 +336,372 @@ int upload(void *dst, const void *src, size_t bytes, hipStream_t st)
 
 int upload_sims(vfp_batch *b) { return upload(b->d_sd, b->sd.data(), sizeof(SimDev) * b->count, b->stream); }
 
-int rebuild_units(vfp_batch *b)
+template <typename T>
+int upload_vec(vfp_batch *b, T *&dev, size_t &cap, const std::vector<T> &v)
 {
-    b->active.clear();
-    for (int s = 0; s < b->count; ++s)
-        if (b->hs[s].active) b->active.push_back(s);
+    if (v.size() > cap) {
+        if (dev) HIPCHK(hipFree(dev));
+        dev = nullptr;
+        cap = 0;
+        HIPCHK(hipMalloc(&dev, sizeof(T) * v.size()));
+        cap = v.size();
+    }
+    return v.empty() ? VFP_OK : upload(dev, v.data(), sizeof(T) * v.size(), b->stream);
+}
+
+// the FP32-storage forms on the staged kernel: split tick (wake launch, then
+// step launch) or fused tick (one launch)
+bool staged_wake(const vfp_batch *b, const Phase &ph) { return is_fp32_storage(b->precision) && ph.fast && ph.wake; }
+bool fused_tick(const vfp_batch *b, const Phase &ph) { return staged_wake(b, ph) && b->staged == kStagedFused; }
+
+// Units of the simulations in `sims`, appended in dispatch order: block
+// k*kXcds + x of a launch runs on XCD x (the dispatcher deals blocks
+// round-robin).  Every XCD gets an equal share of each grid size's strips
+// (contiguous runs of strips, so neighbouring strips of a simulation share
+// their halo columns in that XCD's L2), larger grids first; the slot list is
+// padded with empty units (w = 0) where an XCD's share is shorter.
+void lay_out_units(vfp_batch *b, std::vector<int> sims, std::vector<Unit> &out)
+{
+    std::stable_sort(sims.begin(), sims.end(), [&](int x, int y) { return b->hs[x].p.n > b->hs[y].p.n; });
+    std::vector<std::vector<Unit>> xcd(kXcds);
+    int x0 = 0;                              // next XCD to take a remainder strip
+    for (size_t a = 0; a < sims.size();) {
+        const int n = b->hs[sims[a]].p.n;
+        std::vector<Unit> cls;               // strips of every simulation of this grid size
+        for (; a < sims.size() && b->hs[sims[a]].p.n == n; ++a) {
+            const int s = sims[a];
+            const int w = b->staged ? choose_strip_c(n, b->cells, b->rotation) : choose_strip(n, b->cells);
+            const int nu = (n + w - 1) / w;
+            for (int i0 = 0; i0 < n; i0 += w) cls.push_back(Unit{s, i0, std::min(w, n - i0), nu});
+        }
+        // q strips to every XCD and one more to r of them, taken in turn
+        // across the grid sizes so that the remainders do not pile up
+        const size_t q = cls.size() / kXcds, r = cls.size() % kXcds;
+        size_t at = 0;
+        for (int x = 0; x < kXcds; ++x) {
+            const size_t len = q + ((size_t)((x - x0 + kXcds) % kXcds) < r ? 1 : 0);
+            xcd[x].insert(xcd[x].end(), cls.begin() + at, cls.begin() + at + len);
+            at += len;
+        }
+        x0 = (int)((x0 + r) % kXcds);
+    }
+    size_t rounds = 0;
+    for (int x = 0; x < kXcds; ++x) rounds = std::max(rounds, xcd[x].size());
+    for (size_t k = 0; k < rounds; ++k)
+        for (int x = 0; x < kXcds; ++x) out.push_back(k < xcd[x].size() ? xcd[x][k] : Unit{0, 0, 0, 0});
+}
+
+// Item list of the fused tick for one group: its units in dispatch order,
+// then each simulation's wake tiles (w = -1, tile index in i0) in whole rounds
+// of kXcds slots.  A wake tile waits for its simulation's units, which all
+// come before it.  (Wake tiles placed between the units, about one round of
+// resident blocks after their simulation's last unit, measured slower on the
+// 200-simulation scan: 119 against 112 us per tick.)
+void lay_out_items(vfp_batch *b, const Group &g)
+{
+    std::vector<int> nu(b->count, 0);
+    for (size_t k = g.unit_off; k < g.unit_off + g.unit_cnt; ++k)
+        if (b->units[k].w > 0) nu[b->units[k].sim] = b->units[k].nu;
+    b->items.insert(b->items.end(), b->units.begin() + g.unit_off, b->units.begin() + g.unit_off + g.unit_cnt);
+    size_t t = g.tile_off;
+    while (t < g.tile_off + g.tile_cnt) {
+        for (int x = 0; x < kXcds; ++x, ++t) {
+            if (t < g.tile_off + g.tile_cnt) {
+                const WakeTile &w = b->wtiles[t];
+                b->items.push_back(Unit{w.sim, w.tile, -1, nu[w.sim]});
+            } else {
+                b->items.push_back(Unit{0, 0, 0, 0});
+            }
+        }
+    }
+}
+
+void destroy_graphs(vfp_batch *b)
+{
+    for (Phase &ph : b->phases) {
+        for (Group &gr : ph.grp)
+            for (int p = 0; p < 2; ++p) {
+                if (gr.gexec[p]) (void)hipGraphExecDestroy(gr.gexec[p]);
+                if (gr.graph[p]) (void)hipGraphDestroy(gr.graph[p]);
+                gr.gexec[p] = nullptr;
+                gr.graph[p] = nullptr;
+            }
+        ph.graphs = false;
+    }
+}
+
+int capture_graph(vfp_batch *b, Phase &ph, int g, int par);
+
+// Retirement phases from the current state, their device arrays and graphs.
+// Called by create and by every call that changes the set of simulations,
+// their state or the tuning; never by a step call.  Drains the stream first
+// (queued launches may still read the arrays it replaces).
+int rebuild(vfp_batch *b)
+{
+    HIPCHK(hipStreamSynchronize(b->stream));
+    for (int g = 0; g < kMaxGroups - 1; ++g)
+        if (b->xstream[g]) HIPCHK(hipStreamSynchronize(b->xstream[g]));
+    b->forked = false;
+    destroy_graphs(b);
+    b->phases.clear();
+    b->cur = 0;
     b->units.clear();
-    // groups: balance the cells of the active simulations over the streams
-    // (largest grids first, each to the group with the fewest cells so far)
-    b->ngroups = b->timing ? 1 : std::max(1, std::min(b->lanes, (int)b->active.size()));
-    std::vector<int> group(b->count, 0);
-    if (b->ngroups > 1) {
-        std::vector<int> order(b->active);
-        std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return b->hs[x].p.n > b->hs[y].p.n; });
-        double load[kMaxGroups] = {};
-        for (int s : order) {
-            int g = 0;
-            for (int h = 1; h < b->ngroups; ++h)
-                if (load[h] < load[g]) g = h;
-            group[s] = g;
-            load[g] += (double)b->hs[s].p.n * b->hs[s].p.n;
-        }
-    }
-    // Units in dispatch order: block k*kXcds + x of a launch runs on XCD x (the
-    // dispatcher deals blocks round-robin).  Every XCD gets an equal share of
-    // each grid size's strips (contiguous runs of strips, so neighbouring
-    // strips of a simulation share their halo columns in that XCD's L2),
-    // larger grids first; the slot list is padded with empty units (w = 0)
-    // where an XCD's share is shorter than the longest.
-    constexpr int kXcds = 8;
-    for (int g = 0; g < b->ngroups; ++g) {
-        std::vector<int> sims_g;
-        for (int s : b->active)
-            if (group[s] == g) sims_g.push_back(s);
-        std::stable_sort(sims_g.begin(), sims_g.end(), [&](int x, int y) { return b->hs[x].p.n > b->hs[y].p.n; });
-        std::vector<std::vector<Unit>> xcd(kXcds);
-        int x0 = 0;                              // next XCD to take a remainder strip
-        for (size_t a = 0; a < sims_g.size();) {
-            const int n = b->hs[sims_g[a]].p.n;
-            std::vector<Unit> cls;               // strips of every simulation of this grid size
-            for (; a < sims_g.size() && b->hs[sims_g[a]].p.n == n; ++a) {
-                const int s = sims_g[a];
-                const int w = b->staged == 3 ? choose_strip_c(n, b->cells, b->rotation) : choose_strip(n, b->cells);
-                const int o0 = (b->K - 1) / 2;
-                const int SY = b->staged == 2 ? (n >= 256 ? 256 : (n + 63) / 64 * 64) + 2 * kH : kSY;
-                for (int i0 = 0; i0 < n; i0 += w)
-                    cls.push_back(Unit{s, i0, std::min(w, n - i0), (kH - o0) * (SY + 1)});
-            }
-            // q strips to every XCD and one more to r of them, taken in turn
-            // across the grid sizes so that the remainders do not pile up
-            const size_t q = cls.size() / kXcds, r = cls.size() % kXcds;
-            size_t at = 0;
-            for (int x = 0; x < kXcds; ++x) {
-                const size_t len = q + ((size_t)((x - x0 + kXcds) % kXcds) < r ? 1 : 0);
-                xcd[x].insert(xcd[x].end(), cls.begin() + at, cls.begin() + at + len);
-                at += len;
-            }
-            x0 = (int)((x0 + r) % kXcds);
-        }
-        size_t rounds = 0;
-        for (int x = 0; x < kXcds; ++x) rounds = std::max(rounds, xcd[x].size());
-        b->unit_off[g] = b->units.size();
-        for (size_t k = 0; k < rounds; ++k)
-            for (int x = 0; x < kXcds; ++x)
-                b->units.push_back(k < xcd[x].size() ? xcd[x][k] : Unit{0, 0, 0, 0});
-        b->unit_cnt[g] = b->units.size() - b->unit_off[g];
-    }
-    if (b->units.size() > b->units_cap) {
-        if (b->d_units) HIPCHK(hipFree(b->d_units));
-        b->d_units = nullptr;
-        HIPCHK(hipMalloc(&b->d_units, sizeof(Unit) * b->units.size()));
-        b->units_cap = b->units.size();
-    }
-    int rc = VFP_OK;
-    if (!b->units.empty()) rc = upload(b->d_units, b->units.data(), sizeof(Unit) * b->units.size(), b->stream);
-    if (rc) return rc;
-    if (!b->active.empty()) rc = upload(b->d_active, b->active.data(), sizeof(int) * b->active.size(), b->stream);
-    if (rc) return rc;
-    // kernel choice and LDS of the fused step
-    b->fast = b->staged > 0 && is_fp32_storage(b->precision) && !b->active.empty();
-    for (int s : b->active) b->fast = b->fast && b->hs[s].fast;
-    size_t mx = 0;
-    for (const Unit &u : b->units) {
-        const size_t n = b->hs[u.sim].p.n;
-        size_t bytes;
-        if (!b->fast) {
-            bytes = 2 * (size_t)u.w * n * elem_size(b->precision);
-        } else if (b->staged == 1) {
-            bytes = (2 * (size_t)u.w * (n + 2 * kPad) + (size_t)(u.w + 2 * kH) * kSY +
-                     (b->rotation ? (size_t)u.w * kSY : 0)) * 4;
-        } else if (b->staged == 2) {
-            const size_t SY = (n >= 256 ? 256 : (n + 63) / 64 * 64) + 2 * kH;
-            bytes = ((size_t)u.w * (n + 2 * kPad) + (size_t)(u.w + 2 * kH) * SY + (b->rotation ? (size_t)u.w * SY : 0)) * 4;
-        } else {
-            bytes = lds_bytes_c((int)n, u.w, b->rotation);
-        }
-        mx = std::max(mx, bytes);
-    }
-    b->lds_step = mx;
-    if (b->lds_step > 150 * 1024)
-        return fail(VFP_EINVAL, "strip does not fit the workgroup's LDS; lower cells_per_unit");
-    // matrix-core wake tiles
+    b->items.clear();
+    b->actv.clear();
     b->wtiles.clear();
-    b->lds_wake = 0;
-    if (is_fp32_storage(b->precision)) {
-      for (int g = 0; g < b->ngroups; ++g) {
-        b->tile_off[g] = b->wtiles.size();
-        for (int s : b->active) {
-            if (group[s] != g) continue;
-            const int nb = (b->hs[s].p.n + 15) / 16;
-            for (int t = 0; t < (nb + 15) / 16; ++t) {
-                b->wtiles.push_back(WakeTile{s, t, 0, 0});
-                const int I0 = 16 * t;
-                const int dmin = std::max(-(nb - 1), I0 - (nb - 1)), dmax = std::min(nb - 1, I0 + 15);
-                const size_t NR = 16 * (16 + dmax - dmin), NL = 16 * (dmax - dmin) + 31;
-                const size_t NLp = (NL + 1 + 7) & ~(size_t)7;
-                if (b->precision == VFP_FP32)
-                    b->lds_wake = std::max(b->lds_wake, (size_t)(2 * b->hs[s].p.n + 255) * sizeof(float));
-                else
-                    b->lds_wake = std::max(b->lds_wake, (2 * NR + 4 * NLp) * sizeof(uint16_t));
-            }
-        }
-        b->tile_cnt[g] = b->wtiles.size() - b->tile_off[g];
-      }
-        if (b->wtiles.size() > b->wtiles_cap) {
-            if (b->d_wtiles) HIPCHK(hipFree(b->d_wtiles));
-            b->d_wtiles = nullptr;
-            HIPCHK(hipMalloc(&b->d_wtiles, sizeof(WakeTile) * b->wtiles.size()));
-            b->wtiles_cap = b->wtiles.size();
-        }
-        if (!b->wtiles.empty()) {
-            rc = upload(b->d_wtiles, b->wtiles.data(), sizeof(WakeTile) * b->wtiles.size(), b->stream);
-            if (rc) return rc;
+    // simulations whose step budget is used up retire now
+    std::vector<int64_t> ends;
+    for (int s = 0; s < b->count; ++s) {
+        HostSim &h = b->hs[s];
+        if (!h.active || h.p.max_steps <= 0) continue;
+        if (h.steps >= h.p.max_steps) {
+            h.active = false;
+            h.frozen_buf = b->parity;
+        } else {
+            ends.push_back(b->tick + (h.p.max_steps - h.steps));
         }
     }
-    b->units_dirty = false;
-    b->graph_valid = false;
+    std::sort(ends.begin(), ends.end());
+    ends.erase(std::unique(ends.begin(), ends.end()), ends.end());
+    ends.push_back(INT64_MAX);
+    int64_t start = b->tick;
+    for (int64_t e : ends) {
+        Phase ph;
+        ph.start = start;
+        ph.end = e;
+        for (int s = 0; s < b->count; ++s) {
+            const HostSim &h = b->hs[s];
+            if (!h.active) continue;
+            const int64_t rt = h.p.max_steps > 0 ? b->tick + (h.p.max_steps - h.steps) : INT64_MAX;
+            if (rt <= start) continue;
+            ph.active.push_back(s);
+            if (rt == e) ph.retire.push_back(s);
+        }
+        start = e;
+        b->phases.push_back(std::move(ph));
+        if (b->phases.back().active.empty()) break;
+    }
+    if (b->phases.back().end != INT64_MAX || !b->phases.back().active.empty()) {
+        Phase tail;                         // every simulation has retired
+        tail.start = b->phases.back().end;
+        b->phases.push_back(tail);
+    }
+    for (Phase &ph : b->phases) {
+        ph.fast = b->staged > 0 && is_fp32_storage(b->precision) && !ph.active.empty();
+        ph.wake = false;
+        for (int s : ph.active) {
+            ph.fast = ph.fast && b->hs[s].fast;
+            ph.wake = ph.wake || b->sd[s].has_wake;
+        }
+        // groups: balance the cells over the streams (largest grids first, each to
+        // the group with the fewest cells so far); one group while timing
+        ph.ngroups = b->timing ? 1 : std::max(1, std::min(b->lanes, (int)ph.active.size()));
+        std::vector<std::vector<int>> gs(ph.ngroups);
+        {
+            std::vector<int> order(ph.active);
+            std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return b->hs[x].p.n > b->hs[y].p.n; });
+            double load[kMaxGroups] = {};
+            for (int s : order) {
+                int g = 0;
+                for (int h = 1; h < ph.ngroups; ++h)
+                    if (load[h] < load[g]) g = h;
+                gs[g].push_back(s);
+                load[g] += (double)b->hs[s].p.n * b->hs[s].p.n;
+            }
+        }
+        size_t mx = 0;
+        ph.lds_wake = 0;
+        for (int g = 0; g < ph.ngroups; ++g) {
+            Group &gr = ph.grp[g];
+            gr.act_off = b->actv.size();
+            gr.act_cnt = gs[g].size();
+            b->actv.insert(b->actv.end(), gs[g].begin(), gs[g].end());
+            gr.unit_off = b->units.size();
+            lay_out_units(b, gs[g], b->units);
+            gr.unit_cnt = b->units.size() - gr.unit_off;
+            for (size_t k = gr.unit_off; k < gr.unit_off + gr.unit_cnt; ++k) {
+                const Unit &u = b->units[k];
+                if (u.w == 0) continue;
+                const size_t n = b->hs[u.sim].p.n;
+                mx = std::max(mx, ph.fast ? lds_bytes_c((int)n, u.w, b->rotation)
+                                          : 2 * (size_t)u.w * n * elem_size(b->precision));
+            }
+            gr.tile_off = b->wtiles.size();
+            if (is_fp32_storage(b->precision)) {
+                for (int s : gs[g]) {
+                    const int n = b->hs[s].p.n;
+                    const int nt = b->precision == VFP_FP32 ? (n + 255) / 256 : ((n + 15) / 16 + 15) / 16;
+                    for (int t = 0; t < nt; ++t) b->wtiles.push_back(WakeTile{s, t, 0, 0});
+                    ph.lds_wake = std::max(ph.lds_wake, b->precision == VFP_FP32 ? wake_vec_lds(n) : wake_mfma_lds(n));
+                }
+            }
+            gr.tile_cnt = b->wtiles.size() - gr.tile_off;
+            gr.item_off = b->items.size();
+            if (fused_tick(b, ph)) lay_out_items(b, gr);
+            gr.item_cnt = b->items.size() - gr.item_off;
+        }
+        ph.lds_step = fused_tick(b, ph) ? std::max(mx, ph.lds_wake) : mx;
+        if (ph.lds_step > 150 * 1024 || ph.lds_wake > 150 * 1024)
+            return fail(VFP_EINVAL, "strip does not fit the workgroup's LDS; lower cells_per_unit");
+    }
+    // counters of the fused tick start from zero in every new layout (a revived
+    // simulation may have left its last tick's count behind)
+    HIPCHK(hipMemsetAsync(b->d_done, 0, sizeof(unsigned) * 2 * b->count, b->stream));
+    int rc = upload_vec(b, b->d_units, b->units_cap, b->units);
+    if (rc == VFP_OK) rc = upload_vec(b, b->d_items, b->items_cap, b->items);
+    if (rc == VFP_OK) rc = upload_vec(b, b->d_active, b->actv_cap, b->actv);
+    if (rc == VFP_OK) rc = upload_vec(b, b->d_wtiles, b->wtiles_cap, b->wtiles);
+    if (rc) return rc;
+    // graph length: even (keeps the parity) and a multiple of the record cadence
+    b->G = b->every > 0 ? (b->every % 2 ? 2 * b->every : b->every) : 16;
+    while (b->G < 16) b->G *= 2;
+    if (b->use_graph && !b->timing) {
+        int made = 0;
+        for (Phase &ph : b->phases) {
+            if (ph.active.empty() || ph.end - ph.start < b->G) continue;
+            if (made++ == kMaxGraphPhases) break;
+            for (int g = 0; g < ph.ngroups; ++g)
+                for (int par = 0; par < 2; ++par) {
+                    rc = capture_graph(b, ph, g, par);
+                    if (rc) return rc;
+                }
+            ph.graphs = true;
+        }
+    }
+    b->wake_valid = false;
     return VFP_OK;
 }
 
 // ------------------------------------------------------------- launches
+// launch target: one group of a phase on its stream
+struct Target {
+    const Unit *units;
+    int nunits;
+    const Unit *items;
+    int nitems;
+    const WakeTile *tiles;
+    int ntiles;
+    size_t lds_step, lds_wake;
+    hipStream_t st;
+};
+
+Target target(vfp_batch *b, const Phase &ph, int g)
+{
+    const Group &gr = ph.grp[g];
+    return Target{b->d_units + gr.unit_off, (int)gr.unit_cnt, b->d_items ? b->d_items + gr.item_off : nullptr,
+                  (int)gr.item_cnt, b->d_wtiles ? b->d_wtiles + gr.tile_off : nullptr, (int)gr.tile_cnt,
+                  ph.lds_step, ph.lds_wake, g == 0 ? b->stream : b->xstream[g - 1]};
+}
+
 template <typename T, int K, int WAKE, bool CL, int ROT>
-void launch_step_t(vfp_batch *b, int parity)
+void launch_step_t(vfp_batch *b, const Target &t, int parity)
 {
     auto k = [] {
         if constexpr (std::is_same_v<T, int64_t>) return stepfix_kernel<K, WAKE, CL, ROT>;
         else return step_kernel<T, K, WAKE, CL, ROT>;
     }();
     static int cur = 0;
-    lds_limit(k, b->lds_step, cur);
-    hipLaunchKernelGGL(k, dim3((unsigned)b->cur_nunits), dim3(kThreads), b->lds_step, b->cur_stream,
-                       b->d_sd, b->cur_units, b->cur_nunits, parity);
+    lds_limit(k, t.lds_step, cur);
+    hipLaunchKernelGGL(k, dim3((unsigned)t.nunits), dim3(kThreads), t.lds_step, t.st, b->d_sd, t.units, t.nunits,
+                       parity);
 }
 
 template <int K, int WAKE, bool CL, int ROT>
-void launch_step32_t(vfp_batch *b, int parity)
+void launch_step32c_t(vfp_batch *b, const Target &t, int parity)
 {
-    auto k = b->staged == 3   ? step32c_kernel<K, WAKE, CL, ROT>
-             : b->staged == 2 ? step32b_kernel<K, WAKE, CL, ROT>
-                              : step32_kernel<K, WAKE, CL, ROT>;
-    static int cur[4] = {0, 0, 0, 0};
-    lds_limit(k, b->lds_step, cur[b->staged]);
-    hipLaunchKernelGGL(k, dim3((unsigned)b->cur_nunits), dim3(kThreads), b->lds_step, b->cur_stream,
-                       b->d_sd, b->cur_units, b->cur_nunits, parity);
+    static int cur = 0;
+    lds_limit(step32c_kernel<K, WAKE, CL, ROT>, t.lds_step, cur);
+    hipLaunchKernelGGL((step32c_kernel<K, WAKE, CL, ROT>), dim3((unsigned)t.nunits), dim3(kThreads), t.lds_step, t.st,
+                       b->d_sd, t.units, t.nunits, parity);
 }
 
+template <int K, bool CL, int ROT, int WK>
+void launch_tick32_t(vfp_batch *b, const Target &t, int parity)
+{
+    static int cur = 0;
+    lds_limit(tick32_kernel<K, CL, ROT, WK>, t.lds_step, cur);
+    hipLaunchKernelGGL((tick32_kernel<K, CL, ROT, WK>), dim3((unsigned)t.nitems), dim3(kThreads), t.lds_step, t.st,
+                       b->d_sd, t.items, t.nitems, parity, b->d_done, b->count, b->d_flag);
+}
+
+template <int K, bool CL, int ROT>
+void launch_tick32_w(vfp_batch *b, const Target &t, int parity)
+{
+    if (b->precision == VFP_MIXED_FP16) launch_tick32_t<K, CL, ROT, TW_FP16>(b, t, parity);
+    else if (b->precision == VFP_MIXED_BF16) launch_tick32_t<K, CL, ROT, TW_BF16>(b, t, parity);
+    else launch_tick32_t<K, CL, ROT, TW_VEC>(b, t, parity);
+}
+
+// the step launch of a tick: kernel by storage type, wake mode, layout and tick form
 template <typename T, int K, int WAKE>
-void launch_step_w(vfp_batch *b, int parity)
+void launch_step_w(vfp_batch *b, const Phase &ph, const Target &t, int parity)
 {
     if constexpr (sizeof(T) == 4) {
-        if (b->fast) {
-            if (b->rotation) {
-                if (b->clamp) launch_step32_t<K, WAKE, true, 1>(b, parity);
-                else launch_step32_t<K, WAKE, false, 1>(b, parity);
+        if (ph.fast) {
+            if (WAKE == WAKE_EXTERNAL && b->staged == kStagedFused) {
+                if (b->rotation) {
+                    if (b->clamp) launch_tick32_w<K, true, 1>(b, t, parity);
+                    else launch_tick32_w<K, false, 1>(b, t, parity);
+                } else {
+                    if (b->clamp) launch_tick32_w<K, true, 0>(b, t, parity);
+                    else launch_tick32_w<K, false, 0>(b, t, parity);
+                }
             } else {
-                if (b->clamp) launch_step32_t<K, WAKE, true, 0>(b, parity);
-                else launch_step32_t<K, WAKE, false, 0>(b, parity);
+                if (b->rotation) {
+                    if (b->clamp) launch_step32c_t<K, WAKE, true, 1>(b, t, parity);
+                    else launch_step32c_t<K, WAKE, false, 1>(b, t, parity);
+                } else {
+                    if (b->clamp) launch_step32c_t<K, WAKE, true, 0>(b, t, parity);
+                    else launch_step32c_t<K, WAKE, false, 0>(b, t, parity);
+                }
             }
             return;
         }
     }
     if (b->clamp) {
-        if (b->rotation) launch_step_t<T, K, WAKE, true, 1>(b, parity);
-        else launch_step_t<T, K, WAKE, true, 0>(b, parity);
+        if (b->rotation) launch_step_t<T, K, WAKE, true, 1>(b, t, parity);
+        else launch_step_t<T, K, WAKE, true, 0>(b, t, parity);
     } else {
-        if (b->rotation) launch_step_t<T, K, WAKE, false, 1>(b, parity);
-        else launch_step_t<T, K, WAKE, false, 0>(b, parity);
+        if (b->rotation) launch_step_t<T, K, WAKE, false, 1>(b, t, parity);
+        else launch_step_t<T, K, WAKE, false, 0>(b, t, parity);
     }
 }
 
 template <typename T, int WAKE>
-void launch_step_k(vfp_batch *b, int parity)
+void launch_step_k(vfp_batch *b, const Phase &ph, const Target &t, int parity)
 {
-    if (b->K == 3) launch_step_w<T, 3, WAKE>(b, parity);
-    else launch_step_w<T, 4, WAKE>(b, parity);
+    if (b->K == 3) launch_step_w<T, 3, WAKE>(b, ph, t, parity);
+    else launch_step_w<T, 4, WAKE>(b, ph, t, parity);
 }
 
-bool any_wake(const vfp_batch *b)
+// the wake of every simulation of the target from the column sums in buffer
+// `parity` (a launch of its own: every tick of the split form and of the
+// generic FP32 kernel, and the first tick of the fused form)
+void launch_wake(vfp_batch *b, const Target &t, int parity)
 {
-    for (int s : b->active)
-        if (b->sd[s].has_wake) return true;
-    return false;
-}
-
-// record an event of the timing pool on the handle's stream
-int timing_event(vfp_batch *b, int *idx)
-{
-    hipEvent_t e;
-    HIPCHK(hipEventCreate(&e));
-    HIPCHK(hipEventRecord(e, b->stream));
-    b->ev_pool.push_back(e);
-    *idx = (int)b->ev_pool.size() - 1;
-    return VFP_OK;
-}
-
-// the kernels of one tick for the group selected by select_group()
-int launch_tick_group(vfp_batch *b, int parity)
-{
-    if (b->cur_nunits == 0) return VFP_OK;
-    const bool wake = any_wake(b);
-    int t0 = -1, t1 = -1, t2 = -1;
-    const bool mfma = is_fp32_storage(b->precision) && wake;      // a separate wake kernel
-    if (b->timing) {
-        int rc = timing_event(b, &t0);
-        if (rc) return rc;
-    }
-    if (b->precision == VFP_FP64) {
-        if (wake) launch_step_k<double, WAKE_FUSED>(b, parity);
-        else launch_step_k<double, WAKE_NONE>(b, parity);
-    } else if (b->precision == VFP_FIXED) {
-        if (wake) launch_step_k<int64_t, WAKE_FUSED>(b, parity);
-        else launch_step_k<int64_t, WAKE_NONE>(b, parity);
-    } else if (!wake) {
-        launch_step_k<float, WAKE_NONE>(b, parity);
-    } else if (b->precision == VFP_FP32) {
+    if (t.ntiles == 0) return;
+    if (b->precision == VFP_FP32) {
         static int cur = 0;
-        lds_limit(wake_vec_kernel, b->lds_wake, cur);
-        if (b->cur_ntiles > 0)
-            hipLaunchKernelGGL(wake_vec_kernel, dim3((unsigned)b->cur_ntiles), dim3(kThreads), b->lds_wake,
-                               b->cur_stream, b->d_sd, b->cur_tiles, parity);
-        if (b->timing) {
-            int rc = timing_event(b, &t1);
-            if (rc) return rc;
-        }
-        launch_step_k<float, WAKE_EXTERNAL>(b, parity);
+        lds_limit(wake_vec_kernel, t.lds_wake, cur);
+        hipLaunchKernelGGL(wake_vec_kernel, dim3((unsigned)t.ntiles), dim3(kThreads), t.lds_wake, t.st, b->d_sd,
+                           t.tiles, parity);
     } else {
         const bool fp16 = b->precision == VFP_MIXED_FP16;
         auto wk = fp16 ? wake_mfma2_kernel<true> : wake_mfma2_kernel<false>;
         static int cur16 = 0, cur8 = 0;
-        lds_limit(wk, b->lds_wake, fp16 ? cur16 : cur8);
-        if (b->cur_ntiles > 0)
-            hipLaunchKernelGGL(wk, dim3((unsigned)b->cur_ntiles), dim3(kThreads), b->lds_wake, b->cur_stream,
-                               b->d_sd, b->cur_tiles, parity);
-        if (b->timing) {
-            int rc = timing_event(b, &t1);
-            if (rc) return rc;
-        }
-        launch_step_k<float, WAKE_EXTERNAL>(b, parity);
+        lds_limit(wk, t.lds_wake, fp16 ? cur16 : cur8);
+        hipLaunchKernelGGL(wk, dim3((unsigned)t.ntiles), dim3(kThreads), t.lds_wake, t.st, b->d_sd, t.tiles, parity);
     }
-    HIPCHK(hipGetLastError());
-    if (b->timing) {
-        int rc = timing_event(b, &t2);
-        if (rc) return rc;
-        if (mfma) {
-            b->ev_wake.push_back({t0, t1});
-            b->ev_step.push_back({t1, t2});
-        } else {
-            b->ev_step.push_back({t0, t2});
-        }
-    }
-    return VFP_OK;
-}
-
-void select_group(vfp_batch *b, int g)
-{
-    b->cur_units = b->d_units + b->unit_off[g];
-    b->cur_nunits = (int)b->unit_cnt[g];
-    b->cur_tiles = b->d_wtiles ? b->d_wtiles + b->tile_off[g] : nullptr;
-    b->cur_ntiles = (int)b->tile_cnt[g];
-    b->cur_stream = g == 0 ? b->stream : b->xstream[g - 1];
 }
 
 // the other groups' streams start after the work already queued on the batch's stream
-int fork_streams(vfp_batch *b)
+int fork_streams(vfp_batch *b, const Phase &ph)
 {
-    if (b->ngroups < 2 || b->forked) return VFP_OK;
+    if (ph.ngroups < 2 || b->forked) return VFP_OK;
     HIPCHK(hipEventRecord(b->ev_fork, b->stream));
-    for (int g = 1; g < b->ngroups; ++g) HIPCHK(hipStreamWaitEvent(b->xstream[g - 1], b->ev_fork, 0));
+    for (int g = 1; g < ph.ngroups; ++g) HIPCHK(hipStreamWaitEvent(b->xstream[g - 1], b->ev_fork, 0));
     b->forked = true;
-    b->forked_groups = b->ngroups;
+    b->forked_groups = ph.ngroups;
     return VFP_OK;
 }
 
@@ -618,61 +717,103 @@ int join_streams(vfp_batch *b)
     return VFP_OK;
 }
 
-// one tick of every group (forks the second stream if needed; does not join)
-int launch_tick(vfp_batch *b, int parity)
+// next event of the timing pool (recorded on the batch's stream), or -1 once
+// the pool is used up
+int timing_event(vfp_batch *b)
 {
-    if (b->units.empty()) return VFP_OK;
-    int rc = fork_streams(b);
-    for (int g = 0; g < b->ngroups && rc == VFP_OK; ++g) {
-        select_group(b, g);
-        rc = launch_tick_group(b, parity);
+    if (b->ev_used >= b->ev_pool.size()) return -1;
+    const int idx = (int)b->ev_used++;
+    return hipEventRecord(b->ev_pool[idx], b->stream) == hipSuccess ? idx : -1;
+}
+
+// the launches of one tick of group g that reads buffer `parity`, on the
+// group's stream: the FP32-storage forms on the staged kernel run a wake
+// launch then a step launch (split) or one launch (fused); FP64 and fixed
+// point one step launch with the wake slice inside; the generic FP32 kernel a
+// wake launch then its step launch
+int launch_group_tick(vfp_batch *b, const Phase &ph, int g, int parity)
+{
+    const bool sep_wake = is_fp32_storage(b->precision) && ph.wake && !fused_tick(b, ph);
+    const Target t = target(b, ph, g);
+    if (t.nunits == 0) return VFP_OK;
+    const bool timed = b->timing;             // timing runs in one group, on the batch's stream
+    const int t0 = timed ? timing_event(b) : -1;
+    int t1 = -1;
+    if (b->precision == VFP_FP64) {
+        if (ph.wake) launch_step_k<double, WAKE_FUSED>(b, ph, t, parity);
+        else launch_step_k<double, WAKE_NONE>(b, ph, t, parity);
+    } else if (b->precision == VFP_FIXED) {
+        if (ph.wake) launch_step_k<int64_t, WAKE_FUSED>(b, ph, t, parity);
+        else launch_step_k<int64_t, WAKE_NONE>(b, ph, t, parity);
+    } else if (!ph.wake) {
+        launch_step_k<float, WAKE_NONE>(b, ph, t, parity);
+    } else {
+        if (sep_wake) {
+            launch_wake(b, t, parity);
+            if (timed) t1 = timing_event(b);
+        }
+        launch_step_k<float, WAKE_EXTERNAL>(b, ph, t, parity);
     }
-    return rc;
+    HIPCHK(hipGetLastError());
+    if (timed) {
+        const int t2 = timing_event(b);
+        if (t0 >= 0 && t2 >= 0) {
+            if (sep_wake && t1 >= 0) {
+                b->ev_wake.push_back({t0, t1});
+                b->ev_step.push_back({t1, t2});
+            } else if (!sep_wake) {
+                b->ev_step.push_back({t0, t2});
+            }
+        }
+    }
+    return VFP_OK;
 }
 
 // stats over an explicit list of (simulation, buffer) pairs
-int launch_stats(vfp_batch *b, const int *d_which, const int *d_buf, int cnt, int record)
+int launch_stats(vfp_batch *b, const int *d_which, const int *d_buf, int cnt, int record, hipStream_t st)
 {
     if (cnt == 0) return VFP_OK;
     // per-column sums over 16-column tiles of the largest grid
     const int maxn = (int)(b->lds_stats / (2 * sizeof(double)));
     const dim3 mgrid((unsigned)((maxn + 15) / 16), (unsigned)cnt);
     if (b->precision == VFP_FP64)
-        hipLaunchKernelGGL(moments_kernel<double>, mgrid, dim3(kThreads), 0, b->stream, b->d_sd, d_which, d_buf);
+        hipLaunchKernelGGL(moments_kernel<double>, mgrid, dim3(kThreads), 0, st, b->d_sd, d_which, d_buf);
     else if (b->precision == VFP_FIXED)
-        hipLaunchKernelGGL(moments_kernel<int64_t>, mgrid, dim3(kThreads), 0, b->stream, b->d_sd, d_which, d_buf);
+        hipLaunchKernelGGL(moments_kernel<int64_t>, mgrid, dim3(kThreads), 0, st, b->d_sd, d_which, d_buf);
     else
-        hipLaunchKernelGGL(moments_kernel<float>, mgrid, dim3(kThreads), 0, b->stream, b->d_sd, d_which, d_buf);
+        hipLaunchKernelGGL(moments_kernel<float>, mgrid, dim3(kThreads), 0, st, b->d_sd, d_which, d_buf);
     if (b->precision == VFP_FP64) {
         static int cur = 0;
         lds_limit(stats_kernel<double>, b->lds_stats, cur);
-        hipLaunchKernelGGL(stats_kernel<double>, dim3(cnt), dim3(kThreads), b->lds_stats, b->stream, b->d_sd,
+        hipLaunchKernelGGL(stats_kernel<double>, dim3(cnt), dim3(kThreads), b->lds_stats, st, b->d_sd,
                            d_which, d_buf);
     } else if (b->precision == VFP_FIXED) {
         static int cur = 0;
         lds_limit(stats_kernel<int64_t>, b->lds_stats, cur);
-        hipLaunchKernelGGL(stats_kernel<int64_t>, dim3(cnt), dim3(kThreads), b->lds_stats, b->stream, b->d_sd,
+        hipLaunchKernelGGL(stats_kernel<int64_t>, dim3(cnt), dim3(kThreads), b->lds_stats, st, b->d_sd,
                            d_which, d_buf);
     } else {
         static int cur = 0;
         lds_limit(stats_kernel<float>, b->lds_stats, cur);
-        hipLaunchKernelGGL(stats_kernel<float>, dim3(cnt), dim3(kThreads), b->lds_stats, b->stream, b->d_sd,
+        hipLaunchKernelGGL(stats_kernel<float>, dim3(cnt), dim3(kThreads), b->lds_stats, st, b->d_sd,
                            d_which, d_buf);
     }
     // the wake of every listed simulation over row tiles of the largest grid, then P
     const unsigned tiles = (unsigned)((maxn + 63) / 64);
-    hipLaunchKernelGGL(wakev_kernel, dim3(tiles, (unsigned)cnt), dim3(kThreads), 0, b->stream, b->d_sd, d_which);
-    hipLaunchKernelGGL(power_kernel, dim3(cnt), dim3(kThreads), 0, b->stream, b->d_sd, d_which, b->rec_base,
+    hipLaunchKernelGGL(wakev_kernel, dim3(tiles, (unsigned)cnt), dim3(kThreads), 0, st, b->d_sd, d_which);
+    hipLaunchKernelGGL(power_kernel, dim3(cnt), dim3(kThreads), 0, st, b->d_sd, d_which, b->rec_base,
                        b->every, record);
     HIPCHK(hipGetLastError());
     return VFP_OK;
 }
 
-// record launch after a tick that read buffer `par`: every active simulation's
-// fresh state is in buffer par ^ 1
-int launch_record(vfp_batch *b, int par)
+// record launch of group g after a tick that read buffer `par`: the group's
+// simulations' fresh states are in buffer par ^ 1
+int launch_record(vfp_batch *b, const Phase &ph, int g, int par)
 {
-    return launch_stats(b, b->d_active, b->d_buf01 + (par ^ 1) * b->count, (int)b->active.size(), 1);
+    const Group &gr = ph.grp[g];
+    return launch_stats(b, b->d_active + gr.act_off, b->d_buf01 + (par ^ 1) * b->count, (int)gr.act_cnt, 1,
+                        g == 0 ? b->stream : b->xstream[g - 1]);
 }
 
 // d_idx[0..count) = all simulations, d_idx[count..2count) = their buffers
@@ -690,7 +831,7 @@ int refresh_stats(vfp_batch *b)
 {
     int rc = stage_all_indices(b);
     if (rc) return rc;
-    rc = launch_stats(b, b->d_idx, b->d_idx + b->count, b->count, 0);
+    rc = launch_stats(b, b->d_idx, b->d_idx + b->count, b->count, 0, b->stream);
     if (rc) return rc;
     HIPCHK(hipStreamSynchronize(b->stream));
     return VFP_OK;
@@ -699,121 +840,135 @@ int refresh_stats(vfp_batch *b)
 int check_finite(vfp_batch *b, int s)
 {
     double bad = 0.0;
+    int late = 0;
     HIPCHK(hipMemcpy(&bad, (double *)(b->arena + b->hs[s].off_stat) + 7, sizeof(double), hipMemcpyDeviceToHost));
+    HIPCHK(hipMemcpy(&late, b->d_flag, sizeof(int), hipMemcpyDeviceToHost));
+    if (late != 0) return fail(VFP_EDEVICE, "a wake tile's wait for its simulation's units exceeded its bound");
     if (bad != 0.0) return fail(VFP_EDEVICE, "non-finite density or wake detected");
     return VFP_OK;
 }
 
-// one direct tick (plus the record launch when due)
-int direct_tick(vfp_batch *b)
+// the launches of one tick of group g at tick position `tk` reading buffer
+// `par`, plus the group's record launch when due
+int enqueue_group_tick(vfp_batch *b, const Phase &ph, int g, int par, int64_t tk)
 {
-    int rc = launch_tick(b, b->parity);
-    if (rc == VFP_OK) rc = join_streams(b);
-    if (rc) return rc;
-    if (b->every > 0 && ((b->tick + 1 - b->rec_base) % b->every) == 0) rc = launch_record(b, b->parity);
+    int rc = launch_group_tick(b, ph, g, par);
+    if (rc == VFP_OK && b->every > 0 && ((tk + 1 - b->rec_base) % b->every) == 0) rc = launch_record(b, ph, g, par);
     return rc;
 }
 
-// capture G ticks starting at the current tick and parity
-int capture_graph(vfp_batch *b, int G)
+// one tick of every group (the groups forked from the batch's stream first)
+int enqueue_tick(vfp_batch *b, const Phase &ph, int par, int64_t tk)
 {
-    if (b->gexec) { (void)hipGraphExecDestroy(b->gexec); b->gexec = nullptr; }
-    if (b->graph) { (void)hipGraphDestroy(b->graph); b->graph = nullptr; }
-    HIPCHK(hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
-    int par = b->parity;
+    int rc = fork_streams(b, ph);
+    for (int g = 0; g < ph.ngroups && rc == VFP_OK; ++g) rc = enqueue_group_tick(b, ph, g, par, tk);
+    return rc;
+}
+
+// capture G ticks of group g of phase ph starting at parity par, on the
+// group's stream alone; the graph is replayed only at ticks aligned with the
+// record cadence, so record positions are those of a start at rec_base
+int capture_graph(vfp_batch *b, Phase &ph, int g, int par)
+{
+    const int p0 = par;
+    hipStream_t st = g == 0 ? b->stream : b->xstream[g - 1];
+    HIPCHK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
     int rc = VFP_OK;
-    for (int t = 0; t < G && rc == VFP_OK; ++t) {
-        rc = launch_tick(b, par);
-        if (rc == VFP_OK && b->every > 0 && ((b->tick + t + 1 - b->rec_base) % b->every) == 0) {
-            rc = join_streams(b);
-            if (rc == VFP_OK) rc = launch_record(b, par);
-        }
+    for (int t = 0; t < b->G && rc == VFP_OK; ++t) {
+        rc = enqueue_group_tick(b, ph, g, par, b->rec_base + t);
         par ^= 1;
     }
-    if (rc == VFP_OK) rc = join_streams(b);
-    b->forked = false;
-    hipGraph_t g = nullptr;
-    const hipError_t e = hipStreamEndCapture(b->stream, &g);
-    if (rc) { if (g) (void)hipGraphDestroy(g); return rc; }
+    hipGraph_t gr = nullptr;
+    const hipError_t e = hipStreamEndCapture(st, &gr);
+    if (rc) { if (gr) (void)hipGraphDestroy(gr); return rc; }
     if (e != hipSuccess) return fail(VFP_EDEVICE, std::string("graph capture: ") + hipGetErrorString(e));
-    b->graph = g;
-    HIPCHK(hipGraphInstantiate(&b->gexec, g, nullptr, nullptr, 0));
-    b->graph_ticks = G;
-    b->graph_parity = b->parity;
-    b->graph_valid = true;
+    ph.grp[g].graph[p0] = gr;
+    HIPCHK(hipGraphInstantiate(&ph.grp[g].gexec[p0], gr, nullptr, nullptr, 0));
     return VFP_OK;
 }
 
+// the first fused tick after a state change needs the wake of the current state
+int prime_wake(vfp_batch *b, const Phase &ph)
+{
+    int rc = fork_streams(b, ph);
+    for (int g = 0; g < ph.ngroups && rc == VFP_OK; ++g) launch_wake(b, target(b, ph, g), b->parity);
+    if (rc == VFP_OK) HIPCHK(hipGetLastError());
+    return rc;
+}
+
+// Enqueue nticks ticks: graph replays where a whole graph fits before the
+// next retirement (and starts on the record cadence), single ticks otherwise;
+// retirements switch to the next prepared phase.  The groups run forked on
+// their streams and are joined into the batch's stream at the end of the
+// call.  Host bookkeeping and enqueued work only: no allocation, no
+// synchronisation.
 int advance(vfp_batch *b, int64_t nticks)
 {
     if (nticks < 0) return fail(VFP_EINVAL, "negative step count");
-    int rc;
-    // graph length: even (keeps the parity) and a multiple of the record cadence
-    int G = 0;
-    if (b->use_graph && !b->timing) {
-        G = b->every > 0 ? (b->every % 2 ? 2 * b->every : b->every) : 16;
-        while (G < 16) G *= 2;
-    }
-    while (nticks > 0) {
-        if (b->units_dirty) {
-            rc = rebuild_units(b);
-            if (rc) return rc;
-        }
-        if (b->active.empty()) return VFP_OK;
-        // ticks until the next retirement
-        int64_t until = nticks;
-        for (int s : b->active) {
-            const int64_t ms = b->hs[s].p.max_steps;
-            if (ms > 0) until = std::min(until, ms - b->hs[s].steps);
-        }
-        if (until <= 0) {
-            for (int s : b->active)
-                if (b->hs[s].p.max_steps > 0 && b->hs[s].steps >= b->hs[s].p.max_steps) {
-                    b->hs[s].active = false;
-                    b->hs[s].frozen_buf = b->parity;
-                }
-            b->units_dirty = true;
-            continue;
-        }
+    int rc = VFP_OK;
+    while (nticks > 0 && rc == VFP_OK) {
+        Phase &ph = b->phases[b->cur];
+        if (ph.active.empty()) break;                  // every simulation has retired
+        const int64_t until = std::min(nticks, ph.end - b->tick);
+        const bool fused = fused_tick(b, ph);
         int64_t done = 0;
         while (done < until) {
+            if (fused && !b->wake_valid) {
+                rc = prime_wake(b, ph);                // the wake of the current state, once
+                if (rc) break;
+                b->wake_valid = true;
+            }
             const int64_t left = until - done;
             const bool aligned = b->every == 0 || ((b->tick - b->rec_base) % b->every) == 0;
-            if (G > 0 && left >= G && aligned) {
-                if (!b->graph_valid || b->graph_ticks != G || b->graph_parity != b->parity) {
-                    rc = capture_graph(b, G);
-                    if (rc) return rc;
-                }
-                HIPCHK(hipGraphLaunch(b->gexec, b->stream));
-                b->tick += G;
-                done += G;
+            if (ph.graphs && !b->timing && left >= b->G && aligned) {
+                rc = fork_streams(b, ph);
+                for (int g = 0; g < ph.ngroups && rc == VFP_OK; ++g)
+                    if (hipGraphLaunch(ph.grp[g].gexec[b->parity], g == 0 ? b->stream : b->xstream[g - 1]) !=
+                        hipSuccess)
+                        rc = fail(VFP_EDEVICE, "graph launch failed");
+                if (rc) break;
+                b->tick += b->G;
+                done += b->G;
             } else {
-                rc = direct_tick(b);
-                if (rc) return rc;
+                rc = enqueue_tick(b, ph, b->parity, b->tick);
+                if (rc) break;
                 b->parity ^= 1;
                 ++b->tick;
                 ++done;
             }
+            // a fused tick leaves the next tick's wake; the other forms do not rely on it
+            b->wake_valid = fused;
         }
-        for (int s : b->active) b->hs[s].steps += done;
+        for (int s : ph.active) b->hs[s].steps += done;
         nticks -= done;
+        if (b->tick == ph.end) {
+            for (int s : ph.retire) {
+                b->hs[s].active = false;
+                b->hs[s].frozen_buf = b->parity;
+            }
+            ++b->cur;
+            if (rc == VFP_OK) rc = join_streams(b);    // the next phase forks its own groups
+        }
     }
-    return VFP_OK;
+    const int jrc = join_streams(b);                   // the call ends with everything on the batch's stream
+    return rc ? rc : jrc;
 }
 
 void free_batch(vfp_batch *b)
 {
     if (!b) return;
     if (b->stream) (void)hipStreamSynchronize(b->stream);
-    if (b->gexec) (void)hipGraphExecDestroy(b->gexec);
-    if (b->graph) (void)hipGraphDestroy(b->graph);
+    destroy_graphs(b);
     if (b->own_arena && b->arena) (void)hipFree(b->arena);
     if (b->d_sd) (void)hipFree(b->d_sd);
     if (b->d_units) (void)hipFree(b->d_units);
+    if (b->d_items) (void)hipFree(b->d_items);
     if (b->d_active) (void)hipFree(b->d_active);
+    if (b->d_wtiles) (void)hipFree(b->d_wtiles);
+    if (b->d_done) (void)hipFree(b->d_done);
+    if (b->d_flag) (void)hipFree(b->d_flag);
     if (b->d_idx) (void)hipFree(b->d_idx);
     if (b->d_buf01) (void)hipFree(b->d_buf01);
-    if (b->d_wtiles) (void)hipFree(b->d_wtiles);
     if (b->d_ring) (void)hipFree(b->d_ring);
     if (b->d_ring_rows) (void)hipFree(b->d_ring_rows);
     if (b->d_stage) (void)hipFree(b->d_stage);
@@ -926,10 +1081,8 @@ int upload_psi(vfp_batch *b, int s, const double *psi, bool gaussian)
             return fail(VFP_EINVAL, "initial density must have a positive, finite charge");
         b->sd[s].Q0 = Q0;
         b->sd[s].step0 = b->tick;
-        rc = upload_sims(b);
-        if (rc) return rc;
-        b->graph_valid = false;
-        return VFP_OK;
+        b->wake_valid = false;
+        return upload_sims(b);
     }
     // Q0 = dq*dp*sum(psi0) of the FP64 input (stat[0] is scratch here)
     double *q0dev = (double *)(b->arena + h.off_stat);
@@ -942,10 +1095,8 @@ int upload_psi(vfp_batch *b, int s, const double *psi, bool gaussian)
     if (!(Q0 > 0.0) || !std::isfinite(Q0)) return fail(VFP_EINVAL, "initial density must have a positive, finite charge");
     b->sd[s].Q0 = Q0;
     b->sd[s].step0 = b->tick;
-    rc = upload_sims(b);
-    if (rc) return rc;
-    b->graph_valid = false;
-    return VFP_OK;
+    b->wake_valid = false;
+    return upload_sims(b);
 }
 
 int create_impl(const vfp_params *p, int32_t count, void *stream, void *ws, size_t ws_bytes, bool plain,
@@ -1018,10 +1169,13 @@ int create_impl(const vfp_params *p, int32_t count, void *stream, void *ws, size
     int rc = VFP_OK;
     auto bail = [&](int code) { free_batch(b); return code; };
     if (hipMalloc(&b->d_sd, sizeof(SimDev) * count) != hipSuccess ||
-        hipMalloc(&b->d_active, sizeof(int) * count) != hipSuccess ||
+        hipMalloc(&b->d_done, sizeof(unsigned) * 2 * count) != hipSuccess ||
+        hipMalloc(&b->d_flag, sizeof(int)) != hipSuccess ||
         hipMalloc(&b->d_idx, sizeof(int) * 2 * count) != hipSuccess ||
         hipMalloc(&b->d_buf01, sizeof(int) * 2 * count) != hipSuccess)
         return bail(fail(VFP_ENOMEM, "device allocation failed"));
+    if (hipMemsetAsync(b->d_flag, 0, sizeof(int), b->stream) != hipSuccess)
+        return bail(fail(VFP_EDEVICE, "setup failed"));
     {
         std::vector<int> t01(2 * count, 0);
         for (int s = 0; s < count; ++s) t01[count + s] = 1;
@@ -1170,7 +1324,7 @@ int create_impl(const vfp_params *p, int32_t count, void *stream, void *ws, size
             else
                 hipLaunchKernelGGL(wake_split_kernel<false>, dim3(fb), dim3(kThreads), 0, b->stream, n,
                                    (const double *)(b->arena + h.off_wl64), wscale, (uint16_t *)(b->arena + h.off_frag));
-            const double sx[2] = {1.0, wback};
+            const double sx[3] = {1.0, 1.0, wback};
             if (upload(b->arena + h.off_sext, sx, sizeof(sx), b->stream))
                 return bail(fail(VFP_EDEVICE, "fragment setup failed"));
         }
@@ -1181,7 +1335,7 @@ int create_impl(const vfp_params *p, int32_t count, void *stream, void *ws, size
         rc = upload_psi(b, s, p[s].psi0, p[s].psi0 == nullptr);
         if (rc) return bail(rc);
     }
-    rc = rebuild_units(b);
+    rc = rebuild(b);
     if (rc) return bail(rc);
     if (hipStreamSynchronize(b->stream) != hipSuccess) return bail(fail(VFP_EDEVICE, "setup failed"));
     *out = b;
@@ -1243,11 +1397,8 @@ int record_impl(vfp_batch *b, int32_t every, int64_t cap)
         b->rec_cap = cap;
         b->rec_base = b->tick;
     }
-    int rc = upload_sims(b);
-    if (rc) return rc;
-    b->graph_valid = false;
-    HIPCHK(hipStreamSynchronize(b->stream));
-    return VFP_OK;
+    const int rc = upload_sims(b);
+    return rc ? rc : rebuild(b);        // graphs follow the record cadence
 }
 
 int read_record_impl(vfp_batch *b, int s, double *out, int64_t *rows)
@@ -1488,7 +1639,6 @@ int vfp_batch_set_psi(vfp_batch *b, int32_t i, const double *psi)
     b->hs[i].steps = 0;
     if (b->hs[i].p.max_steps > 0 && !b->hs[i].active) {
         b->hs[i].active = true;
-        b->units_dirty = true;
         // a revived simulation rejoins at the batch parity
         if (b->hs[i].frozen_buf != b->parity) {
             const size_t es = elem_size(b->precision);
@@ -1499,7 +1649,7 @@ int vfp_batch_set_psi(vfp_batch *b, int32_t i, const double *psi)
             HIPCHK(hipStreamSynchronize(b->stream));
         }
     }
-    return VFP_OK;
+    return rebuild(b);                  // its retirement tick has moved
 }
 
 int vfp_set_psi(vfp_sim *sim, const double *psi) { return vfp_batch_set_psi(sim, 0, psi); }
@@ -1540,24 +1690,31 @@ int vfp_batch_set_tuning(vfp_batch *b, int32_t cells_per_unit, int32_t use_graph
     if (cells * elem_size(b->precision) * 2 > 128 * 1024)
         return fail(VFP_EINVAL, "cells_per_unit too large for the workgroup's LDS");
     if (cells < 16) return fail(VFP_EINVAL, "cells_per_unit too small");
-    if (staged < 0 || staged > 3) return fail(VFP_EINVAL, "staged must be 0, 1, 2 or 3");
-    HIPCHK(hipStreamSynchronize(b->stream));
+    if (staged < kStagedGeneric || staged > kStagedFused)
+        return fail(VFP_EINVAL, "staged must be 0 (generic kernel), 1 (staged, split tick) or 2 (staged, fused tick)");
+    const int cells0 = b->cells, staged0 = b->staged;
+    const bool graph0 = b->use_graph;
     b->cells = cells;
     b->use_graph = use_graph != 0;
     b->staged = staged;
-    b->units_dirty = true;
-    b->graph_valid = false;
-    return VFP_OK;
+    const int rc = rebuild(b);
+    if (rc == VFP_OK) return VFP_OK;
+    const std::string why = g_err;          // keep the previous tuning
+    b->cells = cells0;
+    b->use_graph = graph0;
+    b->staged = staged0;
+    const int rc2 = rebuild(b);
+    return rc2 ? rc2 : fail(rc, why);
 }
 
 int vfp_batch_set_streams(vfp_batch *b, int32_t groups)
 {
     if (!b || groups < 1 || groups > kMaxGroups) return fail(VFP_EINVAL, "groups must be in [1, 4]");
-    HIPCHK(hipStreamSynchronize(b->stream));
+    const int lanes0 = b->lanes;
     b->lanes = groups;
-    b->units_dirty = true;
-    b->graph_valid = false;
-    return VFP_OK;
+    const int rc = rebuild(b);
+    if (rc) b->lanes = lanes0;
+    return rc;
 }
 
 int vfp_batch_get_tuning(vfp_batch *b, int32_t *cells_per_unit, int32_t *use_graph, int32_t *staged)
@@ -1594,10 +1751,7 @@ int vfp_batch_haissinski(vfp_batch *b, int32_t i, int32_t iters, double alpha)
         return fail(VFP_EINVAL, "invalid arguments");
     HIPCHK(hipStreamSynchronize(b->stream));
     HostSim &h = b->hs[i];
-    if (!h.active) {
-        h.active = true;
-        b->units_dirty = true;
-    }
+    h.active = true;                    // a retired simulation rejoins at the batch parity
     const int buf = b->parity, n = h.p.n;
     const int v[2] = {i, buf};
     int rc = upload(b->d_idx, v, sizeof(v), b->stream);
@@ -1611,8 +1765,8 @@ int vfp_batch_haissinski(vfp_batch *b, int32_t i, int32_t iters, double alpha)
     HIPCHK(hipStreamSynchronize(b->stream));
     b->sd[i].step0 = b->tick;
     h.steps = 0;
-    b->graph_valid = false;
-    return upload_sims(b);
+    rc = upload_sims(b);
+    return rc ? rc : rebuild(b);
 }
 
 int vfp_haissinski(vfp_sim *sim, int32_t iters, double alpha) { return vfp_batch_haissinski(sim, 0, iters, alpha); }
@@ -1628,10 +1782,7 @@ int vfp_batch_seed(vfp_batch *b, int32_t dst, int32_t src)
     HIPCHK(hipStreamSynchronize(b->stream));
     HostSim &hd = b->hs[dst];
     const HostSim &hsrc = b->hs[src];
-    if (!hd.active) {                         // a retired simulation rejoins at the batch parity
-        hd.active = true;
-        b->units_dirty = true;
-    }
+    hd.active = true;                         // a retired simulation rejoins at the batch parity
     const int bs = hsrc.active ? b->parity : hsrc.frozen_buf;
     const int bd = b->parity;
     const size_t nn = (size_t)a.n * a.n, es = elem_size(b->precision);
@@ -1644,8 +1795,8 @@ int vfp_batch_seed(vfp_batch *b, int32_t dst, int32_t src)
     b->sd[dst].Q0 = b->sd[src].Q0;
     b->sd[dst].step0 = b->tick;
     hd.steps = 0;
-    b->graph_valid = false;
-    return upload_sims(b);
+    const int rc = upload_sims(b);
+    return rc ? rc : rebuild(b);
 }
 
 int vfp_batch_last_wake(vfp_batch *b, int32_t i, double *V)
@@ -1653,8 +1804,12 @@ int vfp_batch_last_wake(vfp_batch *b, int32_t i, double *V)
     if (!b || !V || i < 0 || i >= b->count) return fail(VFP_EINVAL, "invalid arguments");
     if (!b->sd[i].has_wake) return fail(VFP_ESTATE, "simulation has no impedance");
     HIPCHK(hipStreamSynchronize(b->stream));
-    std::vector<float> v(b->hs[i].p.n);
-    HIPCHK(hipMemcpy(v.data(), b->arena + b->hs[i].off_vext, v.size() * sizeof(float), hipMemcpyDeviceToHost));
+    // the latest step read the buffer opposite to the one now holding the state
+    const HostSim &h = b->hs[i];
+    const int prev = (h.active ? b->parity : h.frozen_buf) ^ 1;
+    std::vector<float> v(h.p.n);
+    HIPCHK(hipMemcpy(v.data(), b->arena + h.off_vext + (size_t)prev * h.p.n * sizeof(float), v.size() * sizeof(float),
+                     hipMemcpyDeviceToHost));
     for (size_t k = 0; k < v.size(); ++k) V[k] = v[k];
     return VFP_OK;
 }
@@ -1665,12 +1820,15 @@ int vfp_batch_kernel_timing(vfp_batch *b, int32_t enable)
     HIPCHK(hipStreamSynchronize(b->stream));
     for (hipEvent_t e : b->ev_pool) HIPCHK(hipEventDestroy(e));
     b->ev_pool.clear();
+    b->ev_used = 0;
     b->ev_step.clear();
     b->ev_wake.clear();
     b->timing = enable != 0;
-    b->units_dirty = true;        // one stream group while timing
-    b->graph_valid = false;
-    return VFP_OK;
+    if (b->timing) {
+        b->ev_pool.resize(kTimingEvents);
+        for (hipEvent_t &e : b->ev_pool) HIPCHK(hipEventCreate(&e));
+    }
+    return rebuild(b);                  // no graphs while timing
 }
 
 int vfp_batch_kernel_times(vfp_batch *b, double out[4])
@@ -1713,16 +1871,16 @@ int vfp_batch_autotune(vfp_batch *b, int32_t ticks, int32_t *chosen_cells, int32
         HIPCHK(hipMemcpy(save[s].data() + 2 * nn * es + cb, b->arena + h.off_cs[1], cb, hipMemcpyDeviceToHost));
     }
     const int64_t tick0 = b->tick;
-    const int parity0 = b->parity;
-    const int every0 = b->every;
-    const bool timing0 = b->timing;
-    const int staged0 = b->staged, cells0 = b->cells;
-    b->every = 0;   // no records during trials
+    const int parity0 = b->parity, every0 = b->every, staged0 = b->staged, cells0 = b->cells;
+    const bool timing0 = b->timing, graph0 = b->use_graph;
+    b->every = 0;                   // no records, graphs or event timing during the trials
     b->timing = false;
-    std::vector<int> layouts = is_fp32_storage(b->precision) ? std::vector<int>{1, 2, 3} : std::vector<int>{0};
-    const std::vector<int> cand = elem_size(b->precision) == 8 ? std::vector<int>{1024, 2048, 4096, 8192}
-                                                                : std::vector<int>{2048, 4096, 8192, 16384};
-    hipEvent_t e0, e1;
+    b->use_graph = false;
+    const std::vector<int> layouts = is_fp32_storage(b->precision) ? std::vector<int>{kStagedSplit, kStagedFused}
+                                                                    : std::vector<int>{kStagedGeneric};
+    const std::vector<int> cand = es == 8 ? std::vector<int>{1024, 2048, 4096, 8192}
+                                          : std::vector<int>{2048, 4096, 8192, 16384};
+    hipEvent_t e0 = nullptr, e1 = nullptr;
     HIPCHK(hipEventCreate(&e0));
     HIPCHK(hipEventCreate(&e1));
     float best = 1e30f;
@@ -1730,23 +1888,25 @@ int vfp_batch_autotune(vfp_batch *b, int32_t ticks, int32_t *chosen_cells, int32
     int rc = VFP_OK;
     for (int layout : layouts) {
         for (int c : cand) {
-            // every stream group has drained the previous candidate's ticks before its
-            // unit and tile arrays are rewritten
-            rc = join_streams(b);
-            if (rc == VFP_OK && hipStreamSynchronize(b->stream) != hipSuccess) rc = fail(VFP_EDEVICE, "autotune sync failed");
-            if (rc) break;
             b->cells = c;
             b->staged = layout;
-            b->units_dirty = true;
-            rc = rebuild_units(b);
+            rc = rebuild(b);                // drains the previous candidate's ticks first
             if (rc == VFP_EINVAL) { rc = VFP_OK; continue; }   // does not fit the LDS
             if (rc) break;
-            // warm up, then time; the end event waits for every group's ticks
-            for (int t = 0; t < 2 && rc == VFP_OK; ++t) { rc = launch_tick(b, b->parity); b->parity ^= 1; }
-            if (rc == VFP_OK) rc = join_streams(b);
-            if (rc) break;
-            HIPCHK(hipEventRecord(e0, b->stream));
-            for (int t = 0; t < ticks && rc == VFP_OK; ++t) { rc = launch_tick(b, b->parity); b->parity ^= 1; }
+            // trial ticks of the first phase (the whole batch), warm-up then timed;
+            // a phase shorter than the trial is stepped past its end: only the time counts
+            const Phase &ph = b->phases[0];
+            if (ph.active.empty()) break;
+            if (fused_tick(b, ph)) rc = prime_wake(b, ph);
+            for (int t = 0; t < 2 + ticks && rc == VFP_OK; ++t) {
+                if (t == 2) {
+                    rc = join_streams(b);
+                    if (rc == VFP_OK && hipEventRecord(e0, b->stream) != hipSuccess)
+                        rc = fail(VFP_EDEVICE, "autotune event failed");
+                }
+                if (rc == VFP_OK) rc = enqueue_tick(b, ph, b->parity, b->tick);
+                b->parity ^= 1;
+            }
             if (rc == VFP_OK) rc = join_streams(b);
             if (rc) break;
             HIPCHK(hipEventRecord(e1, b->stream));
@@ -1759,12 +1919,10 @@ int vfp_batch_autotune(vfp_batch *b, int32_t ticks, int32_t *chosen_cells, int32
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
-    // restore, after every group's trial ticks have finished (stream-ordered copies)
     {
         const int jrc = join_streams(b);
         if (rc == VFP_OK) rc = jrc;
     }
-    b->forked = false;
     HIPCHK(hipStreamSynchronize(b->stream));
     for (int g = 0; g < kMaxGroups - 1; ++g)
         if (b->xstream[g]) HIPCHK(hipStreamSynchronize(b->xstream[g]));
@@ -1785,11 +1943,12 @@ int vfp_batch_autotune(vfp_batch *b, int32_t ticks, int32_t *chosen_cells, int32
     b->parity = parity0;
     b->every = every0;
     b->timing = timing0;
+    b->use_graph = graph0;
     b->cells = rc ? cells0 : best_c;
     b->staged = rc ? staged0 : best_l;
-    b->units_dirty = true;
-    b->graph_valid = false;
+    const int rc2 = rebuild(b);         // the chosen tuning; the wake is recomputed from the restored state
     if (rc) return rc;
+    if (rc2) return rc2;
     if (chosen_cells) *chosen_cells = best_c;
     if (chosen_staged) *chosen_staged = best_l;
     return VFP_OK;

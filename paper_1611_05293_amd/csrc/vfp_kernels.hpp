@@ -45,8 +45,8 @@ struct SimDev {
     const double *wl64;              // 2n-1 lags, FP64
     const float *wl32;               // 2n-1 lags, FP32
     const uint16_t *wsplit;          // matrix-core wake: reversed hi/lo lag tables (wake_split_kernel)
-    float *vext;                     // wake used by the latest step (n, FP32)
-    double *sext;                    // renormalisation factor used with vext
+    float *vext;                     // [2][n]: vext[p] is the wake of the state held in buffer p (FP32)
+    double *sext;                    // {s of buffer 0, s of buffer 1, inverse lag scale of the hi/lo wake}
     double *rho_out, *v_out;         // FP64 diagnostics (n each)
     const double *zr64;              // Re Z_k, k = 0..M/2 (CSR spectrum)
     double *stat;                    // {Q, <q>, sq, <p>, sp, P, s, bad}
@@ -62,9 +62,12 @@ struct SimDev {
     float fbx, fby, fk1, fe[4], fd0, fd1, fpad;
 };
 
+// A work unit: simulation, first column i0 and width w of its strip.  In the
+// item list of the fused tick, w == 0 is an empty slot and w < 0 a wake tile
+// (tile index in i0); nu is the number of units of the simulation.
 struct Unit {
     int32_t sim, i0, w;
-    int32_t pad;     // staged kernel: LDS index bias (kH - o0) * (kSY + 1)
+    int32_t nu;
 };
 
 // ---------------------------------------------------------------- helpers
@@ -122,6 +125,38 @@ __device__ __forceinline__ double block_sum(double v, double *red)
     __syncthreads();
     return t;
 }
+
+// Column sums shared between the workgroups of one launch (the fused tick's
+// last unit of a simulation reads every unit's sums): written and read as
+// agent-scope relaxed atomics, which on this GPU are stores written through
+// to, and loads served from, the level coherent across the XCDs.  The writer
+// waits for its stores to complete (vmcnt 0) before it counts itself done.
+template <bool COH>
+__device__ __forceinline__ double load_cs(const double *p)
+{
+    typedef const __attribute__((address_space(1))) double gd;
+    if constexpr (COH) return __hip_atomic_load((gd *)p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    else return *(gd *)p;
+}
+// values p[k], k = k0 + q*kThreads (q < kCsBatch), 0 beyond k1: the loads are
+// issued together, so a batch costs one memory round trip
+constexpr int kCsBatch = 8;
+template <bool COH>
+__device__ __forceinline__ void load_cs_batch(const double *p, int k0, int k1, double (&v)[kCsBatch])
+{
+#pragma unroll
+    for (int q = 0; q < kCsBatch; ++q) {
+        const int k = k0 + q * kThreads;
+        v[q] = k < k1 ? load_cs<COH>(p + k) : 0.0;
+    }
+}
+template <bool COH>
+__device__ __forceinline__ void store_cs(double *p, double v)
+{
+    if constexpr (COH) __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    else *p = v;
+}
+__device__ __forceinline__ void wait_stores() { __builtin_amdgcn_s_waitcnt(0x0F70); }   // s_waitcnt vmcnt(0)
 
 // Work units of a step launch: the host lays them out in dispatch order
 // (block k*8 + x runs on XCD x), so block b takes units[b]; slots with
@@ -344,7 +379,7 @@ __global__ __launch_bounds__(kThreads) void step_kernel(const SimDev *__restrict
     // ---- prologue: renormalisation factor and the wake slice
     double s;
     if constexpr (WAKE == WAKE_EXTERNAL) {
-        s = sd.sext[0];
+        s = sd.sext[parity];
     } else {
         double part = 0.0;
         for (int k = tid; k < n; k += kThreads) part += cs[k];
@@ -377,10 +412,10 @@ __global__ __launch_bounds__(kThreads) void step_kernel(const SimDev *__restrict
             double v = 0.0;
             for (int k = 0; k < parts; ++k) v += red[tid * parts + k];
             sh_shift[tid] = sd.S * s * v * sd.kick;      // kick shift in cells
-            sd.vext[i0 + tid] = (float)(sd.S * s * v);   // the wake this step used
+            sd.vext[parity * n + i0 + tid] = (float)(sd.S * s * v);   // the wake this step used
         }
     } else if constexpr (WAKE == WAKE_EXTERNAL) {
-        if (tid < w) sh_shift[tid] = (double)sd.vext[i0 + tid] * sd.kick;
+        if (tid < w) sh_shift[tid] = (double)sd.vext[parity * n + i0 + tid] * sd.kick;
     } else {
         if (tid < w) sh_shift[tid] = 0.0;
     }
@@ -799,20 +834,37 @@ __global__ void wake_split_kernel(int n, const double *__restrict__ wl64, double
     split[3 * LW + idx] = l[1];
 }
 
-constexpr int kWakePer = 16;      // column sums per thread held in registers: n <= 4096
 
-template <bool FP16>
-__global__ __launch_bounds__(kThreads) void wake_mfma2_kernel(const SimDev *__restrict__ sims,
-                                                              const WakeTile *__restrict__ tiles, int parity)
+// LDS bytes of tile `tile` of an n-point wake: the staged rho and lag runs,
+// then (8-byte aligned) the FP64 wave partials and the block reductions.
+__host__ __device__ inline size_t wake_mfma_tile_lds(int n, int tile)
+{
+    const int nb = (n + 15) / 16, I0 = 16 * tile;
+    const int dmin = max(-(nb - 1), I0 - (nb - 1)), dmax = min(nb - 1, I0 + 15);
+    const size_t NR = 16 * (16 + dmax - dmin), NL = 16 * (dmax - dmin) + 31;
+    const size_t NLp = (NL + 1 + 7) & ~(size_t)7;
+    const size_t head = ((2 * NR + 4 * NLp) * sizeof(uint16_t) + 15) & ~(size_t)15;
+    return head + ((size_t)(kWaves - 1) * 64 * 4 + 2 * kWaves) * sizeof(double);
+}
+__host__ __device__ inline size_t wake_mfma_lds(int n)
+{
+    size_t m = 0;
+    const int nb = (n + 15) / 16;
+    for (int t = 0; t < (nb + 15) / 16; ++t) m = m > wake_mfma_tile_lds(n, t) ? m : wake_mfma_tile_lds(n, t);
+    return m;
+}
+
+// One tile of the matrix-core wake of simulation sd from the column sums in
+// buffer `parity`; writes V (vext[parity]) for the tile's rows and, for tile
+// 0, the factor s the wake was made with (sext[parity]).  All LDS is the
+// dynamic buffer.
+template <bool FP16, bool COH = false>
+__device__ void wake_mfma_tile(const SimDev &sd, int tile, int parity)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    __shared__ double red[kThreads];
-    __shared__ double wsum[kWaves - 1][64][4];
-    const WakeTile wt = tiles[blockIdx.x];
-    const SimDev &sd = sims[wt.sim];
     const int n = sd.n, tid = threadIdx.x, lane = tid & 63, nb = (n + 15) / 16;
     const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
-    const int I0 = 16 * wt.tile;
+    const int I0 = 16 * tile;
     const int dmin = max(-(nb - 1), I0 - (nb - 1)), dmax = min(nb - 1, I0 + 15);
     const int Jlo = I0 - dmax;
     const int NR = 16 * (16 + dmax - dmin);            // rho entries of block columns Jlo..Jhi
@@ -822,17 +874,24 @@ __global__ __launch_bounds__(kThreads) void wake_mfma2_kernel(const SimDev *__re
     uint16_t *rhi = (uint16_t *)smem_raw;
     uint16_t *rlo = rhi + NR;
     uint16_t *c0h = rlo + NR, *c0l = c0h + NLp, *c1h = c0l + NLp, *c1l = c1h + NLp;
+    double *wsum = (double *)(smem_raw + (((2 * NR + 4 * NLp) * sizeof(uint16_t) + 15) & ~(size_t)15));
+    double *red = wsum + (kWaves - 1) * 64 * 4;        // 2 * kWaves entries
     typedef const __attribute__((address_space(1))) double gdouble;
     typedef const __attribute__((address_space(1))) uint16_t gu16;
-    gdouble *cs = (gdouble *)sd.colsum[parity];
+    const double *cs = sd.colsum[parity];
 
-    // column sums: each thread loads its share once (n <= kWakePer * kThreads);
-    // issued first so their latency overlaps the lag staging below
-    double v[kWakePer];
+    // charge and largest column sum (each thread adds its columns in order,
+    // then a fixed tree); read again below for the split, so that no
+    // per-thread array of column sums stays live in registers
+    double part = 0.0, mx = 0.0;
+    for (int k0 = tid; k0 < n; k0 += kCsBatch * kThreads) {
+        double v[kCsBatch];
+        load_cs_batch<COH>(cs, k0, n, v);
 #pragma unroll
-    for (int q = 0; q < kWakePer; ++q) {
-        const int k = tid + q * kThreads;
-        v[q] = k < n ? cs[k] : 0.0;
+        for (int q = 0; q < kCsBatch; ++q) {
+            part += v[q];
+            mx = fmax(mx, fabs(v[q]));
+        }
     }
     // lag window: copy 0 (entry y = lag Lhi - y) and copy 1 (shifted by one),
     // hi and lo, each one aligned run of the reversed tables
@@ -852,12 +911,6 @@ __global__ __launch_bounds__(kThreads) void wake_mfma2_kernel(const SimDev *__re
         const int g = 16 * Jlo + k;
         if (g < 0 || g >= n) { rhi[k] = 0; rlo[k] = 0; }
     }
-    double part = 0.0, mx = 0.0;
-#pragma unroll
-    for (int q = 0; q < kWakePer; ++q) {
-        part += v[q];
-        mx = fmax(mx, fabs(v[q]));
-    }
     part = wave_sum(part);
     for (int off = 32; off > 0; off >>= 1) mx = fmax(mx, __shfl_xor(mx, off, 64));
     if (lane == 0) { red[wv] = part; red[kWaves + wv] = mx; }
@@ -871,14 +924,21 @@ __global__ __launch_bounds__(kThreads) void wake_mfma2_kernel(const SimDev *__re
     int e = 0;
     if (FP16 && rmax > 0.0) { frexp(rmax, &e); e = 14 - e; }
     const double rscale = ldexp(s * sd.dp, e);
+    {
+        const int g0 = max(0, 16 * Jlo), g1 = min(n, 16 * Jlo + NR);
+        for (int k0 = g0 + tid; k0 < g1; k0 += kCsBatch * kThreads) {
+            double v[kCsBatch];
+            load_cs_batch<COH>(cs, k0, g1, v);
 #pragma unroll
-    for (int q = 0; q < kWakePer; ++q) {
-        const int g = tid + q * kThreads, k = g - 16 * Jlo;
-        if (g < n && k >= 0 && k < NR) {
-            uint16_t h, l;
-            split16<FP16>((float)(v[q] * rscale), h, l);
-            rhi[k] = h;
-            rlo[k] = l;
+            for (int q = 0; q < kCsBatch; ++q) {
+                const int g = k0 + q * kThreads;
+                if (g < g1) {
+                    uint16_t h, l;
+                    split16<FP16>((float)(v[q] * rscale), h, l);
+                    rhi[g - 16 * Jlo] = h;
+                    rlo[g - 16 * Jlo] = l;
+                }
+            }
         }
     }
     __syncthreads();
@@ -920,47 +980,63 @@ __global__ __launch_bounds__(kThreads) void wake_mfma2_kernel(const SimDev *__re
     double t[4];
     for (int q = 0; q < 4; ++q) t[q] = (double)acc0[q] + ((double)acc1[q] + (double)acc2[q]);
     if (wv > 0)
-        for (int q = 0; q < 4; ++q) wsum[wv - 1][lane][q] = t[q];
+        for (int q = 0; q < 4; ++q) wsum[((wv - 1) * 64 + lane) * 4 + q] = t[q];
     __syncthreads();
     if (wv == 0) {
-        const double outscale = ldexp(sd.S, -e) * sd.sext[1];
+        const double outscale = ldexp(sd.S, -e) * sd.sext[2];
         for (int q = 0; q < 4; ++q) {
             double v = t[q];
-            for (int k = 0; k < kWaves - 1; ++k) v += wsum[k][lane][q];
+            for (int k = 0; k < kWaves - 1; ++k) v += wsum[(k * 64 + lane) * 4 + q];
             const int i = 16 * (I0 + a) + kq + q;
-            if (i < n) sd.vext[i] = (float)(v * outscale);
+            if (i < n) sd.vext[parity * n + i] = (float)(v * outscale);
         }
-        if (wt.tile == 0 && lane == 0) sd.sext[0] = s;
+        if (tile == 0 && lane == 0) sd.sext[parity] = s;
     }
 }
+
+template <bool FP16>
+__global__ __launch_bounds__(kThreads) void wake_mfma2_kernel(const SimDev *__restrict__ sims,
+                                                              const WakeTile *__restrict__ tiles, int parity)
+{
+    const WakeTile wt = tiles[blockIdx.x];
+    wake_mfma_tile<FP16>(sims[wt.sim], wt.tile, parity);
+}
+
 
 // Vector-ALU wake of the FP32 form, one workgroup per (simulation, tile of
 // 256 rows): V_i = S s sum_j w[i-j] rho_j with FP32 products and partial sums
 // over blocks of 32 consecutive j, added in FP64 (Sec. II.B; the same term
 // definition as the fused wake of the FP64/generic kernel).  LDS: rho (n
 // floats) and the tile's lag window (n + 255 floats).
-__global__ __launch_bounds__(kThreads) void wake_vec_kernel(const SimDev *__restrict__ sims,
-                                                            const WakeTile *__restrict__ tiles, int parity)
+// LDS bytes of the vector-ALU wake: rho and a tile's lag window (FP32), then
+// (16-byte aligned) the block reduction
+__host__ __device__ inline size_t wake_vec_head(int n) { return ((size_t)(2 * n + 255) * sizeof(float) + 15) & ~(size_t)15; }
+__host__ __device__ inline size_t wake_vec_lds(int n) { return wake_vec_head(n) + kWaves * sizeof(double); }
+
+template <bool COH = false>
+__device__ void wake_vec_tile(const SimDev &sd, int tile, int parity)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    __shared__ double red[kWaves];
-    const WakeTile wt = tiles[blockIdx.x];
-    const SimDev &sd = sims[wt.sim];
     const int n = sd.n, tid = threadIdx.x, lane = tid & 63;
     const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
-    const int i0 = 256 * wt.tile;
+    const int i0 = 256 * tile;
     float *rho = (float *)smem_raw;
     float *lag = rho + n;                              // lag[k] = w[i0 + k - (n - 1)]
+    double *red = (double *)(smem_raw + wake_vec_head(n));
     typedef const __attribute__((address_space(1))) double gdouble;
     typedef const __attribute__((address_space(1))) float gfloat;
-    gdouble *cs = (gdouble *)sd.colsum[parity];
+    const double *cs = sd.colsum[parity];
     gfloat *wl = (gfloat *)sd.wl32;
     double part = 0.0;
-#pragma unroll 4
-    for (int k = tid; k < n; k += kThreads) {
-        const double v = cs[k];
-        part += v;
-        rho[k] = (float)(sd.dp * v);
+    for (int k0 = tid; k0 < n; k0 += kCsBatch * kThreads) {
+        double v[kCsBatch];
+        load_cs_batch<COH>(cs, k0, n, v);
+#pragma unroll
+        for (int q = 0; q < kCsBatch; ++q) {
+            const int k = k0 + q * kThreads;
+            part += v[q];
+            if (k < n) rho[k] = (float)(sd.dp * v[q]);
+        }
     }
 #pragma unroll 4
     for (int k = tid; k < n + 255; k += kThreads) {
@@ -984,9 +1060,16 @@ __global__ __launch_bounds__(kThreads) void wake_vec_kernel(const SimDev *__rest
             for (int j = jb; j < je; ++j) a32 = fmaf(lw[-j], rho[j], a32);
             acc += a32;
         }
-        sd.vext[i] = (float)(sd.S * s * acc);
+        sd.vext[parity * n + i] = (float)(sd.S * s * acc);
     }
-    if (wt.tile == 0 && tid == 0) sd.sext[0] = s;
+    if (tile == 0 && tid == 0) sd.sext[parity] = s;
+}
+
+__global__ __launch_bounds__(kThreads) void wake_vec_kernel(const SimDev *__restrict__ sims,
+                                                            const WakeTile *__restrict__ tiles, int parity)
+{
+    const WakeTile wt = tiles[blockIdx.x];
+    wake_vec_tile(sims[wt.sim], wt.tile, parity);
 }
 
 // CSR spectrum of the state whose profile the diagnostics kernel left in

@@ -1,7 +1,9 @@
-// vfp_step32c.hpp -- third layout of the FP32 staged step (included by
-// vfp.hip after vfp_step32b.hpp; chosen with the tuning switch).
+// vfp_step32c.hpp -- the FP32 fused step, staged through LDS (included by
+// vfp.hip after vfp_kernels.hpp), and the fused tick of the FP32-storage
+// forms.
 //
-// The same split step as step32_kernel (rotation, kick, damping/diffusion,
+// One workgroup owns a strip of W whole q-columns of one simulation and
+// computes the whole split step for them (rotation, kick, damping/diffusion,
 // FP64 column sums), arranged so that every cell costs as few vector ALU
 // instructions as possible:
 //   * staging: each wave owns whole staged columns; a lane moves four rows
@@ -27,6 +29,37 @@
 #pragma once
 
 namespace vfp {
+
+constexpr int kPad = 8;            // zero rows above and below each rotated column in LDS
+constexpr int kH = 3;              // rotation halo in cells
+
+// Raw buffer over one column of n floats: reads outside [0, n) return 0.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t column_rsrc(const float *col, int n)
+{
+    return __builtin_amdgcn_make_buffer_rsrc((void *)col, (short)0, n * 4, 0x00020000);
+}
+
+// Cubic (K=4, offsets -1..2) and quadratic (K=3, offsets -1..1) Lagrange
+// weights (Sec. III.A), rearranged for fused multiply-adds.
+template <int K>
+__device__ __forceinline__ void lagrange_fma(float t, float *l)
+{
+    if constexpr (K == 4) {
+        const float a = fmaf(t, t, -t);              // t(t-1)
+        const float a6 = a * (1.0f / 6.0f);
+        const float a3 = a * (1.0f / 3.0f);
+        const float b2 = fmaf(a, 0.5f, -1.0f);       // (t+1)(t-2)/2
+        l[0] = fmaf(-a6, t, a3);                     // -t(t-1)(t-2)/6
+        l[1] = fmaf(b2, t, -b2);                     // (t+1)(t-1)(t-2)/2
+        l[2] = -b2 * t;                              // -(t+1)t(t-2)/2
+        l[3] = fmaf(a6, t, a6);                      // (t+1)t(t-1)/6
+    } else {
+        const float a = fmaf(t, t, -t);              // t(t-1)
+        l[0] = 0.5f * a;                             // t(t-1)/2
+        l[1] = fmaf(-t, t, 1.0f);                    // 1 - t^2
+        l[2] = fmaf(0.5f, a, t);                     // t(t+1)/2
+    }
+}
 
 // rows per chunk (a multiple of 64): 256 for the standard rotation, 192 for
 // the Manhattan rotation, whose drifted rows take a third buffer of the
@@ -191,10 +224,10 @@ __device__ __forceinline__ void kick_damp4(const float *a, const float (&w)[4], 
         o[r] = fmaf(C[r][3], g[r + 3], fmaf(C[r][2], g[r + 2], fmaf(C[r][1], g[r + 1], C[r][0] * g[r])));
 }
 
-template <int K, int WAKE, bool CLAMP, int ROT>
-__global__ __launch_bounds__(kThreads) void step32c_kernel(const SimDev *__restrict__ sims,
-                                                           const Unit *__restrict__ units, int nunits,
-                                                           int parity)
+// One work unit (a strip of whole columns of one simulation): reads buffer
+// `parity`, writes the next state and its FP64 column sums to parity ^ 1.
+template <int K, int WAKE, bool CLAMP, int ROT, bool COH = false>
+__device__ __forceinline__ void step32c_unit(const SimDev &sd, const Unit &u, int parity)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     __shared__ double red[kThreads];
@@ -205,9 +238,6 @@ __global__ __launch_bounds__(kThreads) void step32c_kernel(const SimDev *__restr
     __shared__ float2 sh_xy[kMaxStripC];       // per column: ax0 + i*axi, cy0 + i*cyi
     constexpr int o0 = (K - 1) / 2;
 
-    const Unit u = units[blockIdx.x];
-    if (u.w == 0) return;                     // padding slot
-    const SimDev &sd = sims[u.sim];
     const int n = sd.n, W = u.w, i0 = u.i0, tid = threadIdx.x, lane = tid & 63;
     const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int LA = n + 2 * kPad;
@@ -226,7 +256,7 @@ __global__ __launch_bounds__(kThreads) void step32c_kernel(const SimDev *__restr
     // ---- prologue: renormalisation factor, wake slice, kick weights, pads
     double s;
     if constexpr (WAKE == WAKE_EXTERNAL) {
-        s = sd.sext[0];
+        s = sd.sext[parity];
     } else {
         double part = 0.0;
         for (int k = tid; k < n; k += kThreads) part += cs[k];
@@ -266,10 +296,10 @@ __global__ __launch_bounds__(kThreads) void step32c_kernel(const SimDev *__restr
             double v = 0.0;
             for (int k = 0; k < parts; ++k) v += red[tid * parts + k];
             shift = sd.S * s * v * sd.kick;
-            sd.vext[i0 + tid] = (float)(sd.S * s * v);      // the wake this step used
+            sd.vext[parity * n + i0 + tid] = (float)(sd.S * s * v);      // the wake this step used
         }
     } else if constexpr (WAKE == WAKE_EXTERNAL) {
-        if (tid < W) shift = (double)sd.vext[i0 + tid] * sd.kick;
+        if (tid < W) shift = (double)sd.vext[parity * n + i0 + tid] * sd.kick;
     }
     if (tid < W) {
         const double ic = (double)(i0 + tid);
@@ -518,8 +548,75 @@ __global__ __launch_bounds__(kThreads) void step32c_kernel(const SimDev *__restr
         if (c < W)
             for (int k = sub; k < nb * 64; k += g) t += (double)Sp[c * nb * 64 + k];
         for (int off = g >> 1; off > 0; off >>= 1) t += __shfl_xor(t, off, 64);
-        if (c < W && sub == 0) cs_next[i0 + c] = t;
+        if (c < W && sub == 0) store_cs<COH>(cs_next + i0 + c, t);
     }
+}
+
+template <int K, int WAKE, bool CLAMP, int ROT>
+__global__ __launch_bounds__(kThreads) void step32c_kernel(const SimDev *__restrict__ sims,
+                                                           const Unit *__restrict__ units, int nunits,
+                                                           int parity)
+{
+    const Unit u = units[blockIdx.x];
+    if (u.w == 0) return;                     // padding slot
+    step32c_unit<K, WAKE, CLAMP, ROT>(sims[u.sim], u, parity);
+}
+
+// Wake kinds of the fused tick: FP32 vector ALU, FP16 or BF16 hi/lo matrix cores.
+enum TickWake { TW_VEC = 0, TW_FP16 = 1, TW_BF16 = 2 };
+
+// One tick of a batch in one launch.  The grid walks one list of items:
+// work units (w > 0), empty slots (w == 0) and wake tiles (w < 0, tile index
+// in i0).  Every unit steps its strip with the wake V_t and factor s_t of its
+// simulation's current state (vext/sext[parity]), stores its column sums
+// coherently, waits for those stores and counts itself done in
+// done[parity][sim] (no value returned, so the unit's block ends at once).  A
+// wake tile waits until every unit of its simulation has counted itself, then
+// computes its part of V_{t+1} and s_{t+1} from the fresh column sums (Sec.
+// II.B, Eq. "wakepotential": the profile the next step's kick uses) and
+// clears the previous tick's counter done[parity^1][sim].  The host places
+// the wake tiles after all units in the list, so every item a wake tile waits
+// for comes before it and its wait ends once those blocks have run (the tiles
+// are fewer than the resident slots); a wait longer than kWakeSpinLimit polls
+// (about a second, far beyond any tick) sets *flag instead, reported by the
+// host as a device error, and once it is set no wake tile waits any more, so
+// every launch finishes.
+constexpr unsigned kWakeSpinLimit = 1u << 20;
+
+template <int K, bool CLAMP, int ROT, int WK>
+__global__ __launch_bounds__(kThreads) void tick32_kernel(const SimDev *__restrict__ sims,
+                                                          const Unit *__restrict__ items, int nitems, int parity,
+                                                          unsigned *__restrict__ done, int count,
+                                                          int *__restrict__ flag)
+{
+    const Unit u = items[blockIdx.x];
+    if (u.w == 0) return;                     // empty slot
+    const SimDev &sd = sims[u.sim];
+    if (u.w > 0) {
+        step32c_unit<K, WAKE_EXTERNAL, CLAMP, ROT, true>(sd, u, parity);
+        wait_stores();                        // this wave's column sums have reached the coherent level
+        __syncthreads();
+        if (threadIdx.x == 0)
+            (void)__hip_atomic_fetch_add(done + parity * count + u.sim, 1u, __ATOMIC_RELAXED,
+                                         __HIP_MEMORY_SCOPE_AGENT);
+        return;
+    }
+    if (threadIdx.x == 0 && __hip_atomic_load(flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0) {
+        const unsigned *c = done + parity * count + u.sim;
+        unsigned spins = 0;
+        while (__hip_atomic_load(c, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < (unsigned)u.nu) {
+            if (++spins == kWakeSpinLimit) {
+                __hip_atomic_store(flag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                break;
+            }
+            __builtin_amdgcn_s_sleep(1);
+        }
+    }
+    __syncthreads();
+    if constexpr (WK == TW_VEC) wake_vec_tile<true>(sd, u.i0, parity ^ 1);
+    else wake_mfma_tile<WK == TW_FP16, true>(sd, u.i0, parity ^ 1);
+    if (threadIdx.x == 0)
+        __hip_atomic_store(done + (parity ^ 1) * count + u.sim, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 }  // namespace vfp

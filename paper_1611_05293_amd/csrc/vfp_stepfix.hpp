@@ -123,7 +123,7 @@ __global__ __launch_bounds__(kThreads) void stepfix_kernel(const SimDev *__restr
             for (int k = 0; k < parts; ++k) v += red[tid * parts + k];
             const double V = sd.S * v;
             shift = V * sd.th / sd.dp;
-            sd.vext[i0 + tid] = (float)V;             // the wake this step used
+            sd.vext[parity * n + i0 + tid] = (float)V;             // the wake this step used
         }
     }
     if (tid < w) {

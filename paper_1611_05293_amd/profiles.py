@@ -17,8 +17,7 @@ import json
 import os
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-KERNEL_SOURCES = [os.path.join(HERE, "csrc", f) for f in
-                  ("vfp_kernels.hpp", "vfp_step32.hpp", "vfp_step32b.hpp", "vfp_step32c.hpp", "vfp.hip")]
+KERNEL_SOURCES = [os.path.join(HERE, "csrc", f) for f in ("vfp_kernels.hpp", "vfp_step32c.hpp", "vfp.hip")]
 
 
 def sources_hash() -> str:

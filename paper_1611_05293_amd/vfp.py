@@ -102,8 +102,8 @@ def load():
             "vfp_batch_steps_done": (C.c_int, [h, C.c_int32, C.POINTER(C.c_int64)]),
             "vfp_batch_destroy": (None, [h]),
             "vfp_batch_set_tuning": (C.c_int, [h, C.c_int32, C.c_int32, C.c_int32]),
-            "vfp_batch_get_tuning": (C.c_int, [h, C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.POINTER(C.c_int32)]),
             "vfp_batch_set_streams": (C.c_int, [h, C.c_int32]),
+            "vfp_batch_get_tuning": (C.c_int, [h, C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.POINTER(C.c_int32)]),
             "vfp_batch_autotune": (C.c_int, [h, C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]),
             "vfp_device_arch": (C.c_int, [C.c_char_p, C.c_int32]),
             "vfp_batch_kernel_timing": (C.c_int, [h, C.c_int32]),
@@ -283,7 +283,9 @@ class Batch:
         _check(load().vfp_batch_steps_done(self._h, i, C.byref(v)))
         return v.value
 
-    def set_tuning(self, cells_per_unit: int = 0, use_graph: bool = True, staged: int = 3):
+    def set_tuning(self, cells_per_unit: int = 0, use_graph: bool = True, staged: int = 1):
+        """staged: 0 the generic kernel, 1 the LDS-staged kernel with a wake
+        launch per tick (split), 2 the LDS-staged kernel with the one-launch tick (fused)."""
         _check(load().vfp_batch_set_tuning(self._h, int(cells_per_unit), int(bool(use_graph)), int(staged)))
 
     def set_streams(self, groups: int):

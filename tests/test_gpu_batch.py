@@ -70,7 +70,7 @@ def test_autotune_preserves_state_and_results():
     b = vfp.Batch([vfp.sim_kwargs(s, precision="fp32") for s in sims])
     b.step(5)
     cells, layout = b.autotune(ticks=4)
-    assert cells in (2048, 4096, 8192, 16384) and layout in (1, 2, 3)
+    assert cells in (2048, 4096, 8192, 16384) and layout in (1, 2)
     assert all(b.steps_done(i) == 5 for i in range(len(sims)))
     b.step(15)
     for i, s in enumerate(sims):
@@ -163,13 +163,13 @@ def test_haissinski_start_matches_oracle():
 
 
 @pytest.mark.parametrize("K", [3, 4])
-@pytest.mark.parametrize("staged", [0, 1, 2, 3])
+@pytest.mark.parametrize("staged", [0, 1, 2])
 @pytest.mark.parametrize("rotation", [0, 1])
 @pytest.mark.parametrize("clamp", [0, 1])
 def test_kernel_variants_match_oracle(staged, rotation, clamp, K):
-    """Every FP32 kernel layout (generic, staged 64-row chunks, staged 256-row
-    chunks with the merged kick, staged 192-row chunks with 16-byte staging and
-    per-row damping coefficients) and both rotations against the oracle."""
+    """Every FP32 kernel and tick form (generic kernel with a wake launch;
+    LDS-staged kernel with a wake launch; LDS-staged one-launch tick) and both
+    rotations against the oracle."""
     sims = mixed_sims()
     for s in sims:
         s.rotation, s.clamp, s.interp = rotation, clamp, K
@@ -193,11 +193,11 @@ def test_autotune_cache_roundtrip(tmp_path):
     assert len(json.load(open(cache))) == 1
 
 
-@pytest.mark.parametrize("staged", [0, 1, 2, 3])
+@pytest.mark.parametrize("staged", [0, 1, 2])
 def test_strong_kick_every_read_path(staged):
     """Wakes strong enough that the kick moves columns by up to 6 rows (every
     alignment of the aligned kick reads) and by more than the zero pads (the
-    bounds-checked path), in every FP32 layout, against the oracle."""
+    bounds-checked path), in every FP32 kernel and tick form, against the oracle."""
     sims = [small_sim(n=64, steps=160, S=600.0, Pi=0.5, seed=3, lo=-7.0, hi=7.0),
             small_sim(n=64, steps=160, S=1500.0, Pi=0.5, seed=4, lo=-7.0, hi=7.0),
             small_sim(n=128, steps=320, S=600.0, Pi=0.7, seed=5, lo=-8.0, hi=8.0)]
@@ -233,21 +233,27 @@ def test_stream_group_count_is_validated():
 
 
 @pytest.mark.parametrize("precision", ["fp16", "fp32"])
-def test_stream_groups_equal_one(precision):
-    """Splitting a batch over two, three or four streams gives bit-identical
-    states and records to advancing every simulation on one stream (graph
-    replay and direct)."""
+def test_tick_forms_groups_graphs_and_records_agree(precision):
+    """Split and fused ticks, one to four stream groups, graph replay and
+    direct launches, with records and a retirement inside the run: every
+    combination gives bit-identical states, records and step counts."""
     sims = mixed_sims()
+    caps = [0, 23, 0, 51, 0]
     out = []
-    for groups, graph in ((1, True), (2, True), (2, False), (3, True), (4, True), (4, False)):
-        b = vfp.Batch([vfp.sim_kwargs(s, precision=precision) for s in sims])
-        b.set_tuning(0, graph, 3)
+    for staged, groups, graph in ((1, 1, True), (1, 3, True), (1, 4, False), (2, 1, True), (2, 2, True),
+                                  (2, 3, False), (2, 4, True)):
+        b = vfp.Batch([vfp.sim_kwargs(s, precision=precision, max_steps=m) for s, m in zip(sims, caps)])
+        b.set_tuning(0, graph, staged)
         b.set_streams(groups)
         b.record(5, 20)
         b.step(37)
-        out.append(([b.get_psi(i) for i in range(len(sims))], [b.read_record(i) for i in range(len(sims))]))
+        b.step(40)
+        out.append(([b.get_psi(i) for i in range(len(sims))], [b.read_record(i) for i in range(len(sims))],
+                    [b.steps_done(i) for i in range(len(sims))]))
         b.close()
-    for psis, recs in out[1:]:
+    assert out[0][2] == [77, 23, 77, 51, 77]
+    for psis, recs, steps in out[1:]:
+        assert steps == out[0][2]
         for i in range(len(sims)):
             assert np.array_equal(psis[i], out[0][0][i])
             assert np.array_equal(recs[i], out[0][1][i])
