@@ -21,9 +21,13 @@ sys.path.insert(0, ROOT)
 
 METRIC = "phase-space cell-updates/s (N²·steps·sims/s), batched vs plain, at stated L1 err"
 HBM_PEAK_GBS = 8000.0
-# the kernel of a tick: 1 the fused one-launch tick of the FP32-storage forms
-# (LDS-staged step plus the next wake), 0 the generic step kernel (also FP64)
-STEP_KERNEL = {0: "vfp::step_kernel", 1: "vfp::tick32_kernel"}
+# the step kernel of each tick form: 0 the generic kernel (also FP64 and fixed
+# point), 1 the LDS-staged step after its own wake launch (split tick), 2 the
+# one-launch tick (LDS-staged step plus the next wake in the same launch)
+STEP_KERNEL = {0: "vfp::step_kernel", 1: "vfp::step32c_kernel", 2: "vfp::tick32_kernel"}
+TICK_FORM = {0: "a wake launch (FP32 storage) and a step launch of the generic kernel per group",
+             1: "a wake launch then one fused step launch per stream group (split tick)",
+             2: "one launch per stream group: the fused step and the next wake (one-launch tick)"}
 TRAFFIC_FILE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles",
                             "step_kernel_hbm_traffic_scan200_fp16.json")
 
@@ -54,13 +58,20 @@ def workload(name):
 
 
 def _cpu_model():
+    """Model name with family/model/stepping from /proc/cpuinfo (first CPU)."""
+    info = {}
     try:
         for line in open("/proc/cpuinfo"):
-            if line.startswith("model name"):
-                return line.split(":", 1)[1].strip()
+            if ":" in line:
+                k, v = (x.strip() for x in line.split(":", 1))
+                info.setdefault(k, v)
+            elif info:
+                break
     except OSError:
-        pass
-    return "host CPU"
+        return "host CPU"
+    name = info.get("model name", "host CPU")
+    return (f"{name} (family {info.get('cpu family', '?')}, model {info.get('model', '?')}, "
+            f"stepping {info.get('stepping', '?')}, {info.get('cpu MHz', '?')} MHz)")
 
 
 def cpu_baseline(sims, seconds):
@@ -99,23 +110,41 @@ def cpu_baseline(sims, seconds):
         dt = time.perf_counter() - t0
         return cells_tick * ticks / dt, ticks, dt
 
+    def rate_many(budget):
+        """The same simulations advanced together by the oracle's OpenMP loop
+        over simulations (one thread per simulation)."""
+        t0 = time.perf_counter()
+        oracle.run_many([x[0] for x in prep], [x[1] for x in prep], [x[2].copy() for x in prep],
+                        [1] * len(prep), [x[3] for x in prep])
+        one = time.perf_counter() - t0
+        ticks = max(1, int(budget / max(one, 1e-6)))
+        t0 = time.perf_counter()
+        oracle.run_many([x[0] for x in prep], [x[1] for x in prep], [x[2].copy() for x in prep],
+                        [ticks] * len(prep), [x[3] for x in prep])
+        dt = time.perf_counter() - t0
+        return cells_tick * ticks / dt, ticks, dt
+
     threads = oracle.threads()
-    v_all, t_all, dt_all = rate(0.6 * seconds)
+    v_all, t_all, dt_all = rate(0.4 * seconds)
+    v_sims, t_sims, dt_sims = rate_many(0.3 * seconds)
     oracle.set_threads(1)
     try:
-        v_one, t_one, dt_one = rate(0.4 * seconds)
+        v_one, t_one, dt_one = rate(0.3 * seconds)
     finally:
         oracle.set_threads(threads)
     try:
         affinity = len(os.sched_getaffinity(0))
     except (AttributeError, OSError):
         affinity = os.cpu_count()
+    best, how = (v_all, "over columns") if v_all >= v_sims else (v_sims, "over simulations")
     return {
-        "value": v_all, "unit": "cell-updates/s", "cores": threads, "kind": "oracle",
-        "value_1core": v_one, "nproc": os.cpu_count(), "cpus_allowed": affinity, "cpu_model": _cpu_model(),
-        "sample": f"{len(pick)} sims ({'+'.join(f'{counts[n]}x{n}^2' for n in ns)}), a prefix of {t_all} ticks "
-                  f"({dt_all:.1f} s) on {threads} OpenMP threads (loops over columns) and {t_one} ticks "
-                  f"({dt_one:.1f} s) on 1 thread, FP64",
+        "value": best, "unit": "cell-updates/s", "cores": threads, "kind": "oracle",
+        "value_columns": v_all, "value_simulations": v_sims, "value_1core": v_one,
+        "nproc": os.cpu_count(), "cpus_allowed": affinity, "cpu_model": _cpu_model(),
+        "sample": f"{len(pick)} sims ({'+'.join(f'{counts[n]}x{n}^2' for n in ns)}), FP64; all {threads} OpenMP "
+                  f"threads: a prefix of {t_all} ticks ({dt_all:.1f} s) with the loops over columns and {t_sims} "
+                  f"ticks ({dt_sims:.1f} s) with the loop over simulations (value: the faster, {how}); "
+                  f"1 thread: {t_one} ticks ({dt_one:.1f} s)",
     }
 
 
@@ -142,13 +171,18 @@ def timed(b, stream, cells_tick, es, steps):
     import torch
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
+    # untimed re-warm of two graph lengths right before the timed region (the
+    # host-side parity check leaves the GPU idle for seconds), not waited for:
+    # the GPU is still busy with it when the start event is reached, so the
+    # host's launch latency of the timed ticks does not enter the timed region
     torch.cuda.synchronize()
+    b.step(32)
     e0.record(stream)
     b.step(steps)
     e1.record(stream)
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1)
-    kt_ticks = max(20, min(steps, 400))
+    kt_ticks = 300
     b.kernel_timing(True)
     b.step(kt_ticks)
     kt = b.kernel_times()
@@ -177,7 +211,9 @@ def main():
     ap.add_argument("--plain-steps", type=int, default=20)
     ap.add_argument("--autotune", action="store_true")
     ap.add_argument("--no-forms", action="store_true", help="skip the FP32 and Manhattan forms")
-    ap.add_argument("--staged", type=int, default=None, help="FP32 step kernel: 0 generic, 1 staged (fused tick)")
+    ap.add_argument("--staged", type=int, default=None,
+                    help="FP32-storage kernel and tick form: 0 generic, 1 staged split tick, 2 staged one-launch tick")
+    ap.add_argument("--streams", type=int, default=3, choices=[1, 2, 3, 4], help="stream groups of the batch")
     ap.add_argument("--cells", type=int, default=0, help="cells per work unit (0: built-in)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 512 MiB device copy 5 times (scale of the HBM byte counters)")
@@ -229,6 +265,7 @@ def main():
     if args.autotune:
         tuned, layout = b.autotune(ticks=10)
         log(f"autotuned: {tuned} cells per unit, kernel layout {layout}")
+    b.set_streams(args.streams)
     cells_unit, _, args.staged = b.get_tuning()
     b.step(args.warmup)
     torch.cuda.synchronize()
@@ -241,7 +278,8 @@ def main():
         err = parity(b, sims, sorted(by.values()), args.warmup)
         log(f"parity after {args.warmup} ticks, one sim per grid size: max rel-L1 {err:.3e}")
 
-    # timed region: K ticks replayed from the captured graph
+    # timed region: K ticks (graph replays prepared at create; a remainder of
+    # single ticks when K is not a multiple of the graph length)
     r = timed(b, stream, cells_tick, es, args.steps)
     value, ms = r["value"], r["ms"]
     log(f"timed {args.steps} ticks: {ms:.2f} ms -> {value:.4e} cell-updates/s; step kernel "
@@ -252,18 +290,25 @@ def main():
     forms = {}
     if not args.no_forms:
         # the 8-byte forms (FP64, 44-bit fixed point) run the generic kernel and fewer ticks
-        for name, fprec, rot, extra in (("fp32", "fp32", 0, {}), ("manhattan_" + prec, prec, 1, {}),
-                                        ("fp64", "fp64", 0, {}), ("fixed44", "fixed", 0, {"fix_bits": 44})):
+        other = 2 if args.staged == 1 else 1
+        for name, fprec, rot, extra, stg in (
+                ("one_launch_tick" if other == 2 else "split_tick", prec, 0, {}, other),
+                ("fp32", "fp32", 0, {}, args.staged), ("manhattan_" + prec, prec, 1, {}, args.staged),
+                ("fp64", "fp64", 0, {}, 0), ("fixed44", "fixed", 0, {"fix_bits": 44}, 0)):
             if (name.startswith("fp32") and prec == "fp32") or (name == "fp64" and prec == "fp64"):
+                continue
+            if prec in ("fp64", "fixed") and name in ("one_launch_tick", "split_tick"):
                 continue
             wide = fprec in ("fp64", "fixed")
             fsteps = min(args.steps, 50) if wide else args.steps
             fb = vfp.Batch([vfp.sim_kwargs(s_, precision=fprec, rotation=rot, **extra) for s_ in sims],
                            stream=stream, torch_workspace=True)
-            fb.set_tuning(0 if wide else cells_unit, True, 0 if wide else args.staged)
+            fb.set_tuning(0 if wide else cells_unit, True, stg)
+            fb.set_streams(args.streams)
             fb.step(min(args.warmup, 5 if wide else 20))
             fr = timed(fb, stream, cells_tick, 8 if wide else 4, fsteps)
             forms[name] = {"value": fr["value"], "ms_per_step": fr["ms"] / fsteps, "steps": fsteps,
+                           "tick": TICK_FORM[stg], "step_kernel": STEP_KERNEL[stg],
                            "step_kernel_us": fr["step_us"], "wake_kernel_us": fr["wake_us"],
                            "hbm_frac": fr["achieved"] / HBM_PEAK_GBS}
             log(f"form {name}: {fr['value']:.4e} cell-updates/s, step kernel {fr['step_us']:.1f} us "
@@ -333,12 +378,13 @@ def main():
     if not args.no_cpu:
         log("timing the oracle on the host")
         cpu = cpu_baseline(sims, args.cpu_seconds)
-        log(f"oracle: {cpu['value']:.3e} cell-updates/s on {cpu['cores']} threads, {cpu['value_1core']:.3e} on 1 "
+        log(f"oracle: {cpu['value']:.3e} cell-updates/s on {cpu['cores']} threads (columns {cpu['value_columns']:.3e}, "
+            f"simulations {cpu['value_simulations']:.3e}), {cpu['value_1core']:.3e} on 1 "
             f"({cpu['cpu_model']}, nproc {cpu['nproc']})")
 
     # HBM bytes per launch from the stored counter summary, only while it was
     # taken on the current kernel sources (and only for the workload it covers)
-    kname = STEP_KERNEL[args.staged if prec != "fp64" else 0]
+    kname = STEP_KERNEL[args.staged if prec not in ("fp64", "fixed") else 0]
     traffic = None
     if args.workload == "scan200" and prec == "fp16":
         from paper_1611_05293_amd import profiles
@@ -357,16 +403,13 @@ def main():
         "dtype": {"fp64": "f64", "fixed": "int64"}.get(prec, "f32"),
         "data": "synthetic",
         "config": {"workload": desc,
-                   "form": ("batched; a tick is one launch (each work unit steps its strip; the last unit of "
-                            "each simulation computes its next wake), replayed from hipGraphs of 16 ticks"
-                            if args.staged == 1 and prec not in ("fp64", "fixed") else
-                            "batched; a tick is one step launch with the wake slice inside, replayed from hipGraphs"
-                            if prec in ("fp64", "fixed") else
-                            "batched; a tick is a wake launch then a step launch (generic kernel), from hipGraphs"),
+                   "form": ("batched; a tick is, in each stream group, one step launch with the wake slice inside"
+                            if prec in ("fp64", "fixed") else f"batched; a tick is {TICK_FORM[args.staged]}")
+                           + "; ticks replayed from one hipGraph of 16 ticks per stream group, prepared at create",
                    "wake": {"fp16": "FP16 hi/lo MFMA", "bf16": "BF16 hi/lo MFMA",
                             "fp32": "FP32 VALU", "fp64": "FP64 VALU", "fixed": "FP64 VALU"}[prec],
                    "sims": len(sims), "cells_per_tick": cells_tick,
-                   "cells_per_unit": cells_unit, "kernel_layout": args.staged},
+                   "cells_per_unit": cells_unit, "kernel_layout": args.staged, "stream_groups": args.streams},
         "parity": None if err is None else {"max_rel_l1_vs_fp64_oracle": err, "after_steps": args.warmup,
                                             "sims_checked": "one per grid size"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",

@@ -884,6 +884,7 @@ int capture_graph(vfp_batch *b, Phase &ph, int g, int par)
     if (e != hipSuccess) return fail(VFP_EDEVICE, std::string("graph capture: ") + hipGetErrorString(e));
     ph.grp[g].graph[p0] = gr;
     HIPCHK(hipGraphInstantiate(&ph.grp[g].gexec[p0], gr, nullptr, nullptr, 0));
+    HIPCHK(hipGraphUpload(ph.grp[g].gexec[p0], st));      // its first replay starts at once
     return VFP_OK;
 }
 
