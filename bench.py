@@ -148,10 +148,11 @@ def cpu_baseline(sims, seconds):
     }
 
 
-def parity(b, sims, idxs, nsteps):
+def parity(states, sims, nsteps):
+    """Largest rel-L1 of the device states {i: psi} against the oracle after nsteps."""
     import oracle
     worst = 0.0
-    for i in idxs:
+    for i, g in states.items():
         s = sims[i]
         p = oracle.OracleParams.from_recipe(s)
         zr, zi = s.impedance()
@@ -159,7 +160,6 @@ def parity(b, sims, idxs, nsteps):
         psi = s.psi0()
         d = (s.q_max - s.q_min) / (s.n - 1) * (s.p_max - s.p_min) / (s.n - 1)
         ref, _ = oracle.run(p, w, psi, nsteps, d * psi.sum())
-        g = b.get_psi(i)
         worst = max(worst, float(np.abs(g - ref).sum() / np.abs(ref).sum()))
     return worst
 
@@ -171,10 +171,10 @@ def timed(b, stream, cells_tick, es, steps):
     import torch
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
-    # untimed re-warm of two graph lengths right before the timed region (the
-    # host-side parity check leaves the GPU idle for seconds), not waited for:
-    # the GPU is still busy with it when the start event is reached, so the
-    # host's launch latency of the timed ticks does not enter the timed region
+    # untimed re-warm of two graph lengths right before the timed region, not
+    # waited for: the GPU is still busy with it when the start event is
+    # reached, so the host's launch latency of the timed ticks does not enter
+    # the timed region
     torch.cuda.synchronize()
     b.step(32)
     e0.record(stream)
@@ -270,13 +270,13 @@ def main():
     b.step(args.warmup)
     torch.cuda.synchronize()
     log(f"warmup {args.warmup} ticks done")
-    err = None
+    # states of one simulation per grid size after the warm-up, compared with the
+    # oracle after the timed passes (the GPU does not idle during the comparison)
+    states = {}
     if not args.no_parity and args.warmup > 0:
-        by = {}
         for i, s in enumerate(sims):
-            by.setdefault(s.n, i)
-        err = parity(b, sims, sorted(by.values()), args.warmup)
-        log(f"parity after {args.warmup} ticks, one sim per grid size: max rel-L1 {err:.3e}")
+            if all(sims[j].n != s.n for j in states):
+                states[i] = b.get_psi(i)
 
     # timed region: K ticks (graph replays prepared at create; a remainder of
     # single ticks when K is not a multiple of the graph length)
@@ -285,6 +285,10 @@ def main():
     log(f"timed {args.steps} ticks: {ms:.2f} ms -> {value:.4e} cell-updates/s; step kernel "
         f"{r['step_us']:.1f} us, wake kernel {r['wake_us']:.1f} us -> {r['achieved']:.0f} GB/s algorithmic")
     achieved, step_avg_ms, wake_avg_ms, bytes_launch = r["achieved"], r["step_us"] / 1e3, r["wake_us"] / 1e3, r["bytes"]
+    err = None
+    if states:
+        err = parity(states, sims, args.warmup)
+        log(f"parity after {args.warmup} ticks, one sim per grid size: max rel-L1 {err:.3e}")
 
     # the same workload in the other forms (same steps; no parity pass)
     forms = {}

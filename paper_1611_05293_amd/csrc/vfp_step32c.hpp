@@ -12,8 +12,11 @@
 //     consumed after it (register prefetch, kPF4 columns per wave).
 //   * rotation: the source displacement is evaluated in FP32 from per-column
 //     constants, dx = j*bx + (ax0 + i*axi); floor and fraction take one
-//     instruction each; the K*K taps are LDS reads at immediate offsets from
-//     one per-lane address.  The rotated values are stored unscaled.
+//     instruction each.  A wave owns a 64-row block of the chunk and walks
+//     the strip's columns; the K*K taps stay in registers as a window that
+//     slides one stencil column per output column, so a cell reads K taps
+//     from LDS unless its stencil base moved.  The rotated values are stored
+//     unscaled.
 //   * kick + damping/diffusion: a wave owns a block of 256 rows (four per
 //     lane) and walks over the columns, so the four stencil coefficients of
 //     each row (with the renormalisation factor s and the zero rows outside
@@ -77,7 +80,6 @@ __device__ __forceinline__ int cvt_floor(float x)
 }
 
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
-typedef float f32x2 __attribute__((ext_vector_type(2)));
 
 // LDS byte address of a pointer into the workgroup's shared memory
 __device__ __forceinline__ unsigned lds_addr(const void *p)
@@ -85,89 +87,11 @@ __device__ __forceinline__ unsigned lds_addr(const void *p)
     return (unsigned)(uintptr_t)(const __attribute__((address_space(3))) void *)p;
 }
 
-// The K x K stencil taps f[a][b] = S[addr/4 + a*SY + b] of one lane, read at
-// immediate offsets from a single address: stencil column a = 0 (and a = 1
-// while its dword offsets stay below 256) as paired reads, the others as
-// single reads with byte offsets.  The compiler would otherwise form one base
-// register per stencil column.  The reads complete (lgkmcnt 0) before the asm
-// ends.
-template <int K, int SY>
-__device__ __forceinline__ void read_taps(unsigned addr, float (&f)[K][K])
+// An LDS byte address as a pointer into the workgroup's shared memory
+typedef __attribute__((address_space(3))) const float lds_f32;
+__device__ __forceinline__ lds_f32 *lds_ptr(unsigned addr)
 {
-    static_assert(12 * SY + 12 < 65536, "single-read byte offsets are 16 bits");
-    if constexpr (K == 4) {
-        f32x2 t0, t1, t2, t3;
-        float u0, u1, u2, u3, u4, u5, u6, u7;
-        if constexpr (SY + 3 <= 255) {
-            asm volatile(
-                "ds_read2_b32 %0, %12 offset1:1\n\t"
-                "ds_read2_b32 %1, %12 offset0:2 offset1:3\n\t"
-                "ds_read2_b32 %2, %12 offset0:%13 offset1:%14\n\t"
-                "ds_read2_b32 %3, %12 offset0:%15 offset1:%16\n\t"
-                "ds_read_b32 %4, %12 offset:%17\n\t"
-                "ds_read_b32 %5, %12 offset:%18\n\t"
-                "ds_read_b32 %6, %12 offset:%19\n\t"
-                "ds_read_b32 %7, %12 offset:%20\n\t"
-                "ds_read_b32 %8, %12 offset:%21\n\t"
-                "ds_read_b32 %9, %12 offset:%22\n\t"
-                "ds_read_b32 %10, %12 offset:%23\n\t"
-                "ds_read_b32 %11, %12 offset:%24\n\t"
-                "s_waitcnt lgkmcnt(0)"
-                : "=&v"(t0), "=&v"(t1), "=&v"(t2), "=&v"(t3), "=&v"(u0), "=&v"(u1), "=&v"(u2), "=&v"(u3),
-                  "=&v"(u4), "=&v"(u5), "=&v"(u6), "=&v"(u7)
-                : "v"(addr), "i"(SY), "i"(SY + 1), "i"(SY + 2), "i"(SY + 3), "i"(8 * SY), "i"(8 * SY + 4),
-                  "i"(8 * SY + 8), "i"(8 * SY + 12), "i"(12 * SY), "i"(12 * SY + 4), "i"(12 * SY + 8),
-                  "i"(12 * SY + 12));
-        } else {
-            float v0, v1, v2, v3;
-            asm volatile(
-                "ds_read2_b32 %0, %16 offset1:1\n\t"
-                "ds_read2_b32 %1, %16 offset0:2 offset1:3\n\t"
-                "ds_read_b32 %12, %16 offset:%17\n\t"
-                "ds_read_b32 %13, %16 offset:%18\n\t"
-                "ds_read_b32 %14, %16 offset:%19\n\t"
-                "ds_read_b32 %15, %16 offset:%20\n\t"
-                "ds_read_b32 %4, %16 offset:%21\n\t"
-                "ds_read_b32 %5, %16 offset:%22\n\t"
-                "ds_read_b32 %6, %16 offset:%23\n\t"
-                "ds_read_b32 %7, %16 offset:%24\n\t"
-                "ds_read_b32 %8, %16 offset:%25\n\t"
-                "ds_read_b32 %9, %16 offset:%26\n\t"
-                "ds_read_b32 %10, %16 offset:%27\n\t"
-                "ds_read_b32 %11, %16 offset:%28\n\t"
-                "s_waitcnt lgkmcnt(0)"
-                : "=&v"(t0), "=&v"(t1), "=&v"(t2), "=&v"(t3), "=&v"(u0), "=&v"(u1), "=&v"(u2), "=&v"(u3),
-                  "=&v"(u4), "=&v"(u5), "=&v"(u6), "=&v"(u7), "=&v"(v0), "=&v"(v1), "=&v"(v2), "=&v"(v3)
-                : "v"(addr), "i"(4 * SY), "i"(4 * SY + 4), "i"(4 * SY + 8), "i"(4 * SY + 12), "i"(8 * SY),
-                  "i"(8 * SY + 4), "i"(8 * SY + 8), "i"(8 * SY + 12), "i"(12 * SY), "i"(12 * SY + 4),
-                  "i"(12 * SY + 8), "i"(12 * SY + 12));
-            t2 = f32x2{v0, v1};
-            t3 = f32x2{v2, v3};
-        }
-        f[0][0] = t0.x; f[0][1] = t0.y; f[0][2] = t1.x; f[0][3] = t1.y;
-        f[1][0] = t2.x; f[1][1] = t2.y; f[1][2] = t3.x; f[1][3] = t3.y;
-        f[2][0] = u0; f[2][1] = u1; f[2][2] = u2; f[2][3] = u3;
-        f[3][0] = u4; f[3][1] = u5; f[3][2] = u6; f[3][3] = u7;
-    } else {
-        float u0, u1, u2, u3, u4, u5, u6;
-        f32x2 t0;
-        asm volatile(
-            "ds_read2_b32 %0, %8 offset1:1\n\t"
-            "ds_read_b32 %1, %8 offset:8\n\t"
-            "ds_read_b32 %2, %8 offset:%9\n\t"
-            "ds_read_b32 %3, %8 offset:%10\n\t"
-            "ds_read_b32 %4, %8 offset:%11\n\t"
-            "ds_read_b32 %5, %8 offset:%12\n\t"
-            "ds_read_b32 %6, %8 offset:%13\n\t"
-            "ds_read_b32 %7, %8 offset:%14\n\t"
-            "s_waitcnt lgkmcnt(0)"
-            : "=&v"(t0), "=&v"(u0), "=&v"(u1), "=&v"(u2), "=&v"(u3), "=&v"(u4), "=&v"(u5), "=&v"(u6)
-            : "v"(addr), "i"(4 * SY), "i"(4 * SY + 4), "i"(4 * SY + 8), "i"(8 * SY), "i"(8 * SY + 4),
-              "i"(8 * SY + 8));
-        f[0][0] = t0.x; f[0][1] = t0.y; f[0][2] = u0;
-        f[1][0] = u1; f[1][1] = u2; f[1][2] = u3;
-        f[2][0] = u4; f[2][1] = u5; f[2][2] = u6;
-    }
+    return (lds_f32 *)(uintptr_t)addr;
 }
 
 // Tensor Lagrange value of one cell from its K x K taps (clamped to the four
@@ -386,26 +310,57 @@ __device__ __forceinline__ void step32c_unit(const SimDev &sd, const Unit &u, in
         if (j0 + CH < n) load_cols(j0 + CH, 0);
         if constexpr (ROT == 0) {
             const float bxf = sd.fbx, byf = sd.fby;
-            for (int c = wv; c < W; c += kWaves) {
-                const float2 xy = sh_xy[c];
-                const float Xc = xy.x, Yc = xy.y;
-                // LDS byte address of the stencil corner for zero displacement
-                const int cb4 = (int)lds_addr(S + (c + kH - o0) * SY + lane + 4 - o0);
-                float *acol = A + c * LA + kPad + j0 + lane;
+            static_assert(CH == 64 * kWaves, "one 64-row block of the chunk per wave");
+            // wave wv owns rows rb = 64 wv .. rb + 63 of the chunk and walks the
+            // strip's columns in order.  The K x K taps stay in registers as a
+            // window that slides by one stencil column per output column (slot
+            // (c + a) % K holds stencil column a of output column c), so a column
+            // step reads only the K taps of the new stencil column unless the
+            // lane's stencil base (mx, my) moved.
+            const int rb = 64 * wv;
+            const int j = j0 + rb + lane;
+            if (j < n) {
+                const float jf = (float)j;
+                // LDS byte address of staged row rb + lane + 4 - o0 in staged column kH - o0
+                const unsigned rbase = lds_addr(S + (kH - o0) * SY + rb + lane + 4 - o0);
+                float *acol = A + kPad + j;
+                float fs[K][K];
+                int pmx = 0x7fffffff, pmy = 0;
+                for (int c0 = 0; c0 < W; c0 += K) {
 #pragma unroll
-                for (int rb = 0; rb < CH; rb += 64) {
-                    if (j0 + rb >= n) break;
-                    const int j = j0 + rb + lane;
-                    if (j < n) {
-                        const float jf = (float)j;
-                        const float dx = fmaf(jf, bxf, Xc), dy = fmaf(jf, byf, Yc);
-                        const int mx = cvt_floor(dx), my = cvt_floor(dy);
-                        float lx[K], ly[K];
-                        lagrange_fma<K>(__builtin_amdgcn_fractf(dx), lx);
-                        lagrange_fma<K>(__builtin_amdgcn_fractf(dy), ly);
-                        float f[K][K];
-                        read_taps<K, SY>((unsigned)(__mul24(mx, 4 * SY) + cb4 + 4 * rb + 4 * my), f);
-                        acol[rb] = interp_taps<K, CLAMP>(f, lx, ly);
+                    for (int u = 0; u < K; ++u) {
+                        const int c = c0 + u;
+                        if (c < W) {
+                            const float2 xy = sh_xy[c];
+                            const float dx = fmaf(jf, bxf, xy.x), dy = fmaf(jf, byf, xy.y);
+                            const int mx = cvt_floor(dx), my = cvt_floor(dy);
+                            // stencil column a of output column c is staged column c + mx + a + kH - o0
+                            const unsigned base = rbase + 4 * ((c + mx) * SY + my);
+                            if (mx != pmx || my != pmy) {
+#pragma unroll
+                                for (int a = 0; a < K - 1; ++a) {
+                                    const lds_f32 *t = lds_ptr(base + 4 * a * SY);
+#pragma unroll
+                                    for (int b = 0; b < K; ++b) fs[(u + a) % K][b] = t[b];
+                                }
+                            }
+                            {
+                                const lds_f32 *t = lds_ptr(base + 4 * (K - 1) * SY);
+#pragma unroll
+                                for (int b = 0; b < K; ++b) fs[(u + K - 1) % K][b] = t[b];
+                            }
+                            pmx = mx;
+                            pmy = my;
+                            float lx[K], ly[K];
+                            lagrange_fma<K>(__builtin_amdgcn_fractf(dx), lx);
+                            lagrange_fma<K>(__builtin_amdgcn_fractf(dy), ly);
+                            float f[K][K];
+#pragma unroll
+                            for (int a = 0; a < K; ++a)
+#pragma unroll
+                                for (int b = 0; b < K; ++b) f[a][b] = fs[(u + a) % K][b];
+                            acol[c * LA] = interp_taps<K, CLAMP>(f, lx, ly);
+                        }
                     }
                 }
             }
