@@ -81,6 +81,14 @@ __device__ __forceinline__ int cvt_floor(float x)
 
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 
+// a * b + c for a, b within 24-bit signed range (one full-rate instruction)
+__device__ __forceinline__ int mad_i24(int a, int b, int c)
+{
+    int r;
+    asm("v_mad_i32_i24 %0, %1, %2, %3" : "=v"(r) : "v"(a), "s"(b), "v"(c));
+    return r;
+}
+
 // LDS byte address of a pointer into the workgroup's shared memory
 __device__ __forceinline__ unsigned lds_addr(const void *p)
 {
@@ -159,7 +167,7 @@ __device__ __forceinline__ void step32c_unit(const SimDev &sd, const Unit &u, in
     __shared__ int sh_km[kMaxStripC];
     __shared__ float sh_rw[kMaxStripC][4];
     __shared__ int sh_rm[kMaxStripC];
-    __shared__ float2 sh_xy[kMaxStripC];       // per column: ax0 + i*axi, cy0 + i*cyi
+    __shared__ float2 sh_xy[kMaxStripC + 3];   // per column: ax0 + i*axi, cy0 + i*cyi (read in groups of K)
     constexpr int o0 = (K - 1) / 2;
 
     const int n = sd.n, W = u.w, i0 = u.i0, tid = threadIdx.x, lane = tid & 63;
@@ -176,6 +184,56 @@ __device__ __forceinline__ void step32c_unit(const SimDev &sd, const Unit &u, in
     gfloat *__restrict__ dst = (gfloat *)sd.psi[parity ^ 1];
     const double *__restrict__ cs = sd.colsum[parity];
     double *__restrict__ cs_next = sd.colsum[parity ^ 1];
+
+    // ---- staging of CH-row chunks
+    // staged column x is source column i0 - kH + x; its LDS row y is row j0 - 4 + y;
+    // lane l moves rows j0 - 4 + 4l .. +3 (lanes l < Q4).  A staged column of
+    // more than 64 quads (CH > 248) has DX = 4 (Q4 - 64) rows beyond the
+    // lanes' quads (rows j0 + 252 ..); those of prefetched column k are one
+    // row per lane in lanes DX k .. DX k + DX-1 of a single register.
+    constexpr int DX = Q4 > 64 ? 4 * (Q4 - 64) : 0;
+    static_assert(DX * kPF4 <= 64, "the extra rows of every prefetched column fit one register");
+    const int ncolw = (SX - wv + kWaves - 1) / kWaves;
+    const bool lane_ld = lane < Q4;
+    u32x4 pf[kPF4];
+    unsigned pfx = 0;
+    auto load_cols = [&](int j0, int cw0) {
+        // rows above the grid (first chunk, lane 0) get an offset far past the
+        // column instead of a negative one, so the 16-byte range check cannot wrap
+        const int row = j0 - 4 + 4 * lane;
+        const int voff = row >= 0 ? row * 4 : 0x40000000;
+#pragma unroll
+        for (int k = 0; k < kPF4; ++k) {
+            const int x = wv + kWaves * (cw0 + k), gi = i0 - kH + x;
+            if (cw0 + k < ncolw && lane_ld) {
+                const bool ok = gi >= 0 && gi < n;
+                const __amdgpu_buffer_rsrc_t r = column_rsrc(src + (size_t)(ok ? gi : 0) * n, ok ? n : 0);
+                pf[k] = __builtin_amdgcn_raw_buffer_load_b128(r, voff, 0, 0);
+            }
+            if constexpr (DX > 0) {
+                if (cw0 + k < ncolw && lane / DX == k) {
+                    const bool ok = gi >= 0 && gi < n;
+                    const __amdgpu_buffer_rsrc_t r = column_rsrc(src + (size_t)(ok ? gi : 0) * n, ok ? n : 0);
+                    pfx = __builtin_amdgcn_raw_buffer_load_b32(r, (j0 + 252 + lane % DX) * 4, 0, 0);
+                }
+            }
+        }
+    };
+    auto store_cols = [&](int cw0) {
+#pragma unroll
+        for (int k = 0; k < kPF4; ++k) {
+            const int x = wv + kWaves * (cw0 + k);
+            if (cw0 + k < ncolw && lane_ld) *(u32x4 *)(S + x * SY + 4 * lane) = pf[k];
+        }
+        if constexpr (DX > 0) {
+            const int k = lane / DX;
+            if (k < kPF4 && cw0 + k < ncolw)
+                *(unsigned *)(S + (wv + kWaves * (cw0 + k)) * SY + 256 + lane % DX) = pfx;
+        }
+    };
+    // the first chunk's loads go out before the prologue, so that their
+    // latency overlaps the prologue's loads and arithmetic
+    load_cols(0, 0);
 
     // ---- prologue: renormalisation factor, wake slice, kick weights, pads
     double s;
@@ -253,52 +311,6 @@ __device__ __forceinline__ void step32c_unit(const SimDev &sd, const Unit &u, in
     }
 
     // ---- phase R: chunks of CH rows
-    // staged column x is source column i0 - kH + x; its LDS row y is row j0 - 4 + y;
-    // lane l moves rows j0 - 4 + 4l .. +3 (lanes l < Q4).  A staged column of
-    // more than 64 quads (CH > 248) has DX = 4 (Q4 - 64) rows beyond the
-    // lanes' quads (rows j0 + 252 ..); those of prefetched column k are one
-    // row per lane in lanes DX k .. DX k + DX-1 of a single register.
-    constexpr int DX = Q4 > 64 ? 4 * (Q4 - 64) : 0;
-    static_assert(DX * kPF4 <= 64, "the extra rows of every prefetched column fit one register");
-    const int ncolw = (SX - wv + kWaves - 1) / kWaves;
-    const bool lane_ld = lane < Q4;
-    u32x4 pf[kPF4];
-    unsigned pfx = 0;
-    auto load_cols = [&](int j0, int cw0) {
-        // rows above the grid (first chunk, lane 0) get an offset far past the
-        // column instead of a negative one, so the 16-byte range check cannot wrap
-        const int row = j0 - 4 + 4 * lane;
-        const int voff = row >= 0 ? row * 4 : 0x40000000;
-#pragma unroll
-        for (int k = 0; k < kPF4; ++k) {
-            const int x = wv + kWaves * (cw0 + k), gi = i0 - kH + x;
-            if (cw0 + k < ncolw && lane_ld) {
-                const bool ok = gi >= 0 && gi < n;
-                const __amdgpu_buffer_rsrc_t r = column_rsrc(src + (size_t)(ok ? gi : 0) * n, ok ? n : 0);
-                pf[k] = __builtin_amdgcn_raw_buffer_load_b128(r, voff, 0, 0);
-            }
-            if constexpr (DX > 0) {
-                if (cw0 + k < ncolw && lane / DX == k) {
-                    const bool ok = gi >= 0 && gi < n;
-                    const __amdgpu_buffer_rsrc_t r = column_rsrc(src + (size_t)(ok ? gi : 0) * n, ok ? n : 0);
-                    pfx = __builtin_amdgcn_raw_buffer_load_b32(r, (j0 + 252 + lane % DX) * 4, 0, 0);
-                }
-            }
-        }
-    };
-    auto store_cols = [&](int cw0) {
-#pragma unroll
-        for (int k = 0; k < kPF4; ++k) {
-            const int x = wv + kWaves * (cw0 + k);
-            if (cw0 + k < ncolw && lane_ld) *(u32x4 *)(S + x * SY + 4 * lane) = pf[k];
-        }
-        if constexpr (DX > 0) {
-            const int k = lane / DX;
-            if (k < kPF4 && cw0 + k < ncolw)
-                *(unsigned *)(S + (wv + kWaves * (cw0 + k)) * SY + 256 + lane % DX) = pfx;
-        }
-    };
-    load_cols(0, 0);
     for (int j0 = 0; j0 < n; j0 += CH) {
         __syncthreads();
         store_cols(0);
@@ -321,36 +333,45 @@ __device__ __forceinline__ void step32c_unit(const SimDev &sd, const Unit &u, in
             const int j = j0 + rb + lane;
             if (j < n) {
                 const float jf = (float)j;
-                // LDS byte address of staged row rb + lane + 4 - o0 in staged column kH - o0
-                const unsigned rbase = lds_addr(S + (kH - o0) * SY + rb + lane + 4 - o0);
+                // LDS byte address of staged row rb + lane + 4 - o0 in staged column
+                // kH - o0 + K - 1: the last stencil column of output column 0 when the
+                // lane's stencil base is (0, 0)
+                int rbase = (int)lds_addr(S + (kH - o0 + K - 1) * SY + rb + lane + 4 - o0);
+                asm volatile("" : "+v"(rbase));      // kept whole, so the taps sit at offsets 0 .. K-1 of base
                 float *acol = A + kPad + j;
                 float fs[K][K];
-                int pmx = 0x7fffffff, pmy = 0;
+                // window key: the lane's last-stencil-column address without the column
+                // term; it changes exactly when the stencil base (mx, my) moves
+                int pkey = INT_MIN;
                 for (int c0 = 0; c0 < W; c0 += K) {
+                    float2 xy[K];
+#pragma unroll
+                    for (int u = 0; u < K; ++u) xy[u] = sh_xy[c0 + u];
 #pragma unroll
                     for (int u = 0; u < K; ++u) {
                         const int c = c0 + u;
                         if (c < W) {
-                            const float2 xy = sh_xy[c];
-                            const float dx = fmaf(jf, bxf, xy.x), dy = fmaf(jf, byf, xy.y);
+                            const float dx = fmaf(jf, bxf, xy[u].x), dy = fmaf(jf, byf, xy[u].y);
                             const int mx = cvt_floor(dx), my = cvt_floor(dy);
                             // stencil column a of output column c is staged column c + mx + a + kH - o0
-                            const unsigned base = rbase + 4 * ((c + mx) * SY + my);
-                            if (mx != pmx || my != pmy) {
+                            const int key = mad_i24(mx, 4 * SY, (my << 2) + rbase);
+                            int cterm = c * (4 * SY);
+                            asm volatile("" : "+s"(cterm));  // one scalar column term per column
+                            const unsigned base = (unsigned)(key + cterm);
+                            if (key != pkey) {
 #pragma unroll
                                 for (int a = 0; a < K - 1; ++a) {
-                                    const lds_f32 *t = lds_ptr(base + 4 * a * SY);
+                                    const lds_f32 *t = lds_ptr(base - 4 * (K - 1 - a) * SY);
 #pragma unroll
                                     for (int b = 0; b < K; ++b) fs[(u + a) % K][b] = t[b];
                                 }
                             }
                             {
-                                const lds_f32 *t = lds_ptr(base + 4 * (K - 1) * SY);
+                                const lds_f32 *t = lds_ptr(base);
 #pragma unroll
                                 for (int b = 0; b < K; ++b) fs[(u + K - 1) % K][b] = t[b];
                             }
-                            pmx = mx;
-                            pmy = my;
+                            pkey = key;
                             float lx[K], ly[K];
                             lagrange_fma<K>(__builtin_amdgcn_fractf(dx), lx);
                             lagrange_fma<K>(__builtin_amdgcn_fractf(dy), ly);
