@@ -81,6 +81,7 @@ struct HostSim {
         off_v, off_stat, off_zr, off_mom;
     int nb = 0;
     bool fast = false;       // eligible for the LDS-staged FP32 step kernel
+    int halo = 2 * kH;       // staged columns beside a strip (left + right) in that kernel
 };
 
 int choose_strip(int n, int cells)
@@ -92,26 +93,28 @@ int choose_strip(int n, int cells)
 
 // Strip width of the chunked staged layout: at most kMaxStripC columns, the
 // per-(column, 256-row block, lane) partial sums fit the staging buffer
-// (W * nb * 64 <= (W + 2*kH) * staged_rows_c floats), and a grid with more than one
-// chunk keeps every staged column of a wave in the prefetch registers.
+// (W * nb * 64 <= (W + halo) * staged_rows_c floats), and every staged column
+// of a wave travels in the prefetch registers (a fifth column per wave would be
+// loaded and stored with its latency exposed: 128-row grids measured 8 % faster
+// with 12-column strips than with 13).
 // The dynamic LDS of a unit stays under kLdsBudgetC so that five workgroups
 // fit on a compute unit.
 #ifndef VFP_LDS_BUDGET
 #define VFP_LDS_BUDGET (28 * 1024)
 #endif
 constexpr size_t kLdsBudgetC = VFP_LDS_BUDGET;
-size_t lds_bytes_c(int n, int w, int rotation)
+size_t lds_bytes_c(int n, int w, int rotation, int halo)
 {
     const size_t sy = staged_rows_c(rotation);
-    return ((size_t)w * (n + 2 * kPad) + (size_t)(w + 2 * kH) * sy + (rotation ? (size_t)w * sy : 0)) * 4;
+    return ((size_t)w * (n + 2 * kPad) + (size_t)(w + halo) * sy + (rotation ? (size_t)w * sy : 0)) * 4;
 }
-int choose_strip_c(int n, int cells, int rotation)
+int choose_strip_c(int n, int cells, int rotation, int halo)
 {
     int w = std::max(1, std::min(cells / n, std::min(n, kMaxStripC)));
     const int nb = (n + 255) / 256;
-    while (w > 1 && (size_t)w * nb * 64 > (size_t)(w + 2 * kH) * staged_rows_c(rotation)) --w;
-    if (n > chunk_rows_c(rotation)) w = std::min(w, kWaves * kPF4 - 2 * kH);
-    while (w > 1 && lds_bytes_c(n, w, rotation) > kLdsBudgetC) --w;
+    while (w > 1 && (size_t)w * nb * 64 > (size_t)(w + halo) * staged_rows_c(rotation)) --w;
+    w = std::min(w, kWaves * kPF4 - halo);
+    while (w > 1 && lds_bytes_c(n, w, rotation, halo) > kLdsBudgetC) --w;
     return std::max(w, 1);
 }
 
@@ -370,7 +373,7 @@ void lay_out_units(vfp_batch *b, std::vector<int> sims, std::vector<Unit> &out)
         std::vector<Unit> cls;               // strips of every simulation of this grid size
         for (; a < sims.size() && b->hs[sims[a]].p.n == n; ++a) {
             const int s = sims[a];
-            const int w = b->staged ? choose_strip_c(n, b->cells, b->rotation) : choose_strip(n, b->cells);
+            const int w = b->staged ? choose_strip_c(n, b->cells, b->rotation, b->hs[s].halo) : choose_strip(n, b->cells);
             const int nu = (n + w - 1) / w;
             for (int i0 = 0; i0 < n; i0 += w) cls.push_back(Unit{s, i0, std::min(w, n - i0), nu});
         }
@@ -523,7 +526,7 @@ int rebuild(vfp_batch *b)
                 const Unit &u = b->units[k];
                 if (u.w == 0) continue;
                 const size_t n = b->hs[u.sim].p.n;
-                mx = std::max(mx, ph.fast ? lds_bytes_c((int)n, u.w, b->rotation)
+                mx = std::max(mx, ph.fast ? lds_bytes_c((int)n, u.w, b->rotation, b->hs[u.sim].halo)
                                           : 2 * (size_t)u.w * n * elem_size(b->precision));
             }
             gr.tile_off = b->wtiles.size();
@@ -1250,27 +1253,42 @@ int create_impl(const vfp_params *p, int32_t count, void *stream, void *ws, size
         d.zr64 = (const double *)(A + h.off_zr);
         // the staged kernel needs n % 4 == 0 and a rotation source within 2 cells of every
         // node; dx, dy are linear in (i, j), so the corners bound them
-        double lo = 1e300, hi = -1e300;
+        double lo = 1e300, hi = -1e300, lox = 1e300, hix = -1e300;
         for (int ci = 0; ci < 2; ++ci)
             for (int cj = 0; cj < 2; ++cj) {
                 const double i = ci ? q.n - 1 : 0, j = cj ? q.n - 1 : 0;
                 const double dx = d.ax0 + i * d.axi + j * d.bx, dy = d.cy0 + i * d.cyi + j * d.by;
                 lo = std::min(lo, std::min(dx, dy));
                 hi = std::max(hi, std::max(dx, dy));
+                lox = std::min(lox, dx);
+                hix = std::max(hix, dx);
             }
         if (q.rotation == VFP_ROT_MANHATTAN) {
             // drift shifts -tw*(p_min/dp + j), RF kick shifts tk*(q_min/dq + i)
-            lo = 1e300;
-            hi = -1e300;
+            lo = lox = 1e300;
+            hi = hix = -1e300;
+            // (the drift runs over every staged row, four beyond each end of the grid)
             for (int e = 0; e < 2; ++e) {
-                const double k = e ? q.n - 1 : 0;
-                const double a = -d.tw * (d.pm + k), c = d.tk * (q.q_min / d.dq + k);
+                const double k = e ? q.n - 1 : 0, ky = e ? q.n + 3 : -4;
+                const double a = -d.tw * (d.pm + ky), c = d.tk * (q.q_min / d.dq + k);
                 lo = std::min(lo, std::min(a, c));
                 hi = std::max(hi, std::max(a, c));
+                lox = std::min(lox, a);
+                hix = std::max(hix, a);
             }
         }
         // (the margin covers FP32 evaluation of the displacement in the staged kernels)
         b->hs[s].fast = q.n % 4 == 0 && lo > -2.0 + 1e-5 && hi < 2.0 - 1e-5;
+        // staged columns beside a strip: output column c reads source columns
+        // c + floor(dx) - o0 .. c + floor(dx) + K - 1 - o0 (dx: the column
+        // displacement, or the drift shift of the Manhattan rotation)
+        {
+            const int o0 = (q.interp - 1) / 2;
+            const int mlo = (int)std::floor(std::max(lox - 1e-5, -2.0)), mhi = (int)std::floor(std::min(hix + 1e-5, 1.9));
+            d.hl = std::min(kH, std::max(0, o0 - mlo));
+            d.hr = std::min(kH, std::max(0, q.interp - 1 - o0 + mhi));
+            b->hs[s].halo = d.hl + d.hr;
+        }
     }
     b->lds_stats = 2 * (size_t)maxn * sizeof(double);
     HIPCHK(hipMemsetAsync(b->arena, 0, need, b->stream));

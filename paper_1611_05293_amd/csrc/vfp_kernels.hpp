@@ -60,6 +60,9 @@ struct SimDev {
     // -2k1} (k2 = beta*dtheta/dp^2), and the Manhattan drift shift
     // -tw*(pm + row) as fd0 + row*fd1
     float fbx, fby, fk1, fe[4], fd0, fd1, fpad;
+    // staged kernel: source columns staged to the left and right of a strip
+    // (every stencil column the rotation or drift reads, at most kH each side)
+    int32_t hl, hr;
 };
 
 // A work unit: simulation, first column i0 and width w of its strip.  In the

@@ -27,14 +27,14 @@
 // its fixed length keeps all tap offsets compile-time immediates.  Its 66
 // quads (CH = 256) are one per lane plus eight rows that travel one per lane
 // in a shared prefetch register.
-// LDS: A[W][n + 2*kPad], S[W + 2*kH][CH + 8] and, for the Manhattan
+// LDS: A[W][n + 2*kPad], S[W + hl + hr][CH + 8] and, for the Manhattan
 // rotation, Dm[W][CH + 8].
 #pragma once
 
 namespace vfp {
 
 constexpr int kPad = 8;            // zero rows above and below each rotated column in LDS
-constexpr int kH = 3;              // rotation halo in cells
+constexpr int kH = 3;              // largest rotation halo in cells (per side)
 
 // Raw buffer over one column of n floats: reads outside [0, n) return 0.
 __device__ __forceinline__ __amdgpu_buffer_rsrc_t column_rsrc(const float *col, int n)
@@ -174,7 +174,7 @@ __device__ __forceinline__ void step32c_unit(const SimDev &sd, const Unit &u, in
     const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int LA = n + 2 * kPad;
     constexpr int CH = chunk_rows_c(ROT), SY = staged_rows_c(ROT), Q4 = SY / 4;
-    const int SX = W + 2 * kH;
+    const int hl = sd.hl, SX = W + hl + sd.hr;
     float *A = (float *)smem_raw;
     float *S = A + (size_t)W * LA;
     float *Dm = S + (size_t)SX * SY;
@@ -186,7 +186,7 @@ __device__ __forceinline__ void step32c_unit(const SimDev &sd, const Unit &u, in
     double *__restrict__ cs_next = sd.colsum[parity ^ 1];
 
     // ---- staging of CH-row chunks
-    // staged column x is source column i0 - kH + x; its LDS row y is row j0 - 4 + y;
+    // staged column x is source column i0 - hl + x; its LDS row y is row j0 - 4 + y;
     // lane l moves rows j0 - 4 + 4l .. +3 (lanes l < Q4).  A staged column of
     // more than 64 quads (CH > 248) has DX = 4 (Q4 - 64) rows beyond the
     // lanes' quads (rows j0 + 252 ..); those of prefetched column k are one
@@ -204,7 +204,7 @@ __device__ __forceinline__ void step32c_unit(const SimDev &sd, const Unit &u, in
         const int voff = row >= 0 ? row * 4 : 0x40000000;
 #pragma unroll
         for (int k = 0; k < kPF4; ++k) {
-            const int x = wv + kWaves * (cw0 + k), gi = i0 - kH + x;
+            const int x = wv + kWaves * (cw0 + k), gi = i0 - hl + x;
             if (cw0 + k < ncolw && lane_ld) {
                 const bool ok = gi >= 0 && gi < n;
                 const __amdgpu_buffer_rsrc_t r = column_rsrc(src + (size_t)(ok ? gi : 0) * n, ok ? n : 0);
@@ -334,9 +334,9 @@ __device__ __forceinline__ void step32c_unit(const SimDev &sd, const Unit &u, in
             if (j < n) {
                 const float jf = (float)j;
                 // LDS byte address of staged row rb + lane + 4 - o0 in staged column
-                // kH - o0 + K - 1: the last stencil column of output column 0 when the
+                // hl - o0 + K - 1: the last stencil column of output column 0 when the
                 // lane's stencil base is (0, 0)
-                int rbase = (int)lds_addr(S + (kH - o0 + K - 1) * SY + rb + lane + 4 - o0);
+                int rbase = (int)lds_addr(S + (hl - o0 + K - 1) * SY + rb + lane + 4 - o0);
                 asm volatile("" : "+v"(rbase));      // kept whole, so the taps sit at offsets 0 .. K-1 of base
                 float *acol = A + kPad + j;
                 float fs[K][K];
@@ -353,7 +353,7 @@ __device__ __forceinline__ void step32c_unit(const SimDev &sd, const Unit &u, in
                         if (c < W) {
                             const float dx = fmaf(jf, bxf, xy[u].x), dy = fmaf(jf, byf, xy[u].y);
                             const int mx = cvt_floor(dx), my = cvt_floor(dy);
-                            // stencil column a of output column c is staged column c + mx + a + kH - o0
+                            // stencil column a of output column c is staged column c + mx + a + hl - o0
                             const int key = mad_i24(mx, 4 * SY, (my << 2) + rbase);
                             int cterm = c * (4 * SY);
                             asm volatile("" : "+s"(cterm));  // one scalar column term per column
@@ -392,7 +392,7 @@ __device__ __forceinline__ void step32c_unit(const SimDev &sd, const Unit &u, in
                 const int fl = cvt_floor(sh);
                 float l[K];
                 lagrange_fma<K>(__builtin_amdgcn_fractf(sh), l);
-                const float *col = S + (kH + fl - o0) * SY + y;
+                const float *col = S + (hl + fl - o0) * SY + y;
                 for (int c = 0; c < W; ++c, col += SY) {
                     float f[K];
 #pragma unroll
