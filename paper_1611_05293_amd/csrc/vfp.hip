@@ -92,8 +92,9 @@ int choose_strip(int n, int cells)
 }
 
 // Strip width of the chunked staged layout: at most kMaxStripC columns, the
-// per-(column, 256-row block, lane) partial sums fit the staging buffer
-// (W * nb * 64 <= (W + halo) * staged_rows_c floats), and every staged column
+// per-(column, 256-row block, lane) partial sums and the per-(column, block)
+// FP64 moments of a record tick fit the staging buffer
+// (W * nb * (64 + 6) <= (W + halo) * staged_rows_c floats), and every staged column
 // of a wave travels in the prefetch registers (a fifth column per wave would be
 // loaded and stored with its latency exposed: 128-row grids measured 8 % faster
 // with 12-column strips than with 13).
@@ -112,7 +113,7 @@ int choose_strip_c(int n, int cells, int rotation, int halo)
 {
     int w = std::max(1, std::min(cells / n, std::min(n, kMaxStripC)));
     const int nb = (n + 255) / 256;
-    while (w > 1 && (size_t)w * nb * 64 > (size_t)(w + halo) * staged_rows_c(rotation)) --w;
+    while (w > 1 && (size_t)w * nb * (64 + 6) > (size_t)(w + halo) * staged_rows_c(rotation)) --w;
     w = std::min(w, kWaves * kPF4 - halo);
     while (w > 1 && lds_bytes_c(n, w, rotation, halo) > kLdsBudgetC) --w;
     return std::max(w, 1);
@@ -609,13 +610,27 @@ void launch_step_t(vfp_batch *b, const Target &t, int parity)
                        parity);
 }
 
-template <int K, int WAKE, bool CL, int ROT>
+template <int K, int WAKE, bool CL, int ROT, bool MOM = false>
 void launch_step32c_t(vfp_batch *b, const Target &t, int parity)
 {
     static int cur = 0;
-    lds_limit(step32c_kernel<K, WAKE, CL, ROT>, t.lds_step, cur);
-    hipLaunchKernelGGL((step32c_kernel<K, WAKE, CL, ROT>), dim3((unsigned)t.nunits), dim3(kThreads), t.lds_step, t.st,
-                       b->d_sd, t.units, t.nunits, parity);
+    lds_limit(step32c_kernel<K, WAKE, CL, ROT, MOM>, t.lds_step, cur);
+    hipLaunchKernelGGL((step32c_kernel<K, WAKE, CL, ROT, MOM>), dim3((unsigned)t.nunits), dim3(kThreads), t.lds_step,
+                       t.st, b->d_sd, t.units, t.nunits, parity);
+}
+
+// the staged step of the split tick, with the per-column moments of the new
+// state when a record row follows (`mom`)
+template <int K, int WAKE, bool CL, int ROT>
+void launch_step32c_m(vfp_batch *b, const Target &t, int parity, bool mom)
+{
+    if constexpr (WAKE == WAKE_EXTERNAL) {
+        if (mom) {
+            launch_step32c_t<K, WAKE, CL, ROT, true>(b, t, parity);
+            return;
+        }
+    }
+    launch_step32c_t<K, WAKE, CL, ROT>(b, t, parity);
 }
 
 template <int K, bool CL, int ROT, int WK>
@@ -636,8 +651,10 @@ void launch_tick32_w(vfp_batch *b, const Target &t, int parity)
 }
 
 // the step launch of a tick: kernel by storage type, wake mode, layout and tick form
+// (mom: the staged split-tick step also leaves the new state's per-column
+// moments; the caller reads *mom_done to know whether it did)
 template <typename T, int K, int WAKE>
-void launch_step_w(vfp_batch *b, const Phase &ph, const Target &t, int parity)
+void launch_step_w(vfp_batch *b, const Phase &ph, const Target &t, int parity, bool mom, bool *mom_done)
 {
     if constexpr (sizeof(T) == 4) {
         if (ph.fast) {
@@ -651,12 +668,13 @@ void launch_step_w(vfp_batch *b, const Phase &ph, const Target &t, int parity)
                 }
             } else {
                 if (b->rotation) {
-                    if (b->clamp) launch_step32c_t<K, WAKE, true, 1>(b, t, parity);
-                    else launch_step32c_t<K, WAKE, false, 1>(b, t, parity);
+                    if (b->clamp) launch_step32c_m<K, WAKE, true, 1>(b, t, parity, mom);
+                    else launch_step32c_m<K, WAKE, false, 1>(b, t, parity, mom);
                 } else {
-                    if (b->clamp) launch_step32c_t<K, WAKE, true, 0>(b, t, parity);
-                    else launch_step32c_t<K, WAKE, false, 0>(b, t, parity);
+                    if (b->clamp) launch_step32c_m<K, WAKE, true, 0>(b, t, parity, mom);
+                    else launch_step32c_m<K, WAKE, false, 0>(b, t, parity, mom);
                 }
+                if (mom_done) *mom_done = mom && WAKE == WAKE_EXTERNAL;
             }
             return;
         }
@@ -671,10 +689,11 @@ void launch_step_w(vfp_batch *b, const Phase &ph, const Target &t, int parity)
 }
 
 template <typename T, int WAKE>
-void launch_step_k(vfp_batch *b, const Phase &ph, const Target &t, int parity)
+void launch_step_k(vfp_batch *b, const Phase &ph, const Target &t, int parity, bool mom = false,
+                   bool *mom_done = nullptr)
 {
-    if (b->K == 3) launch_step_w<T, 3, WAKE>(b, ph, t, parity);
-    else launch_step_w<T, 4, WAKE>(b, ph, t, parity);
+    if (b->K == 3) launch_step_w<T, 3, WAKE>(b, ph, t, parity, mom, mom_done);
+    else launch_step_w<T, 4, WAKE>(b, ph, t, parity, mom, mom_done);
 }
 
 // the wake of every simulation of the target from the column sums in buffer
@@ -734,7 +753,7 @@ int timing_event(vfp_batch *b)
 // launch then a step launch (split) or one launch (fused); FP64 and fixed
 // point one step launch with the wake slice inside; the generic FP32 kernel a
 // wake launch then its step launch
-int launch_group_tick(vfp_batch *b, const Phase &ph, int g, int parity)
+int launch_group_tick(vfp_batch *b, const Phase &ph, int g, int parity, bool rec = false, bool *mom_done = nullptr)
 {
     const bool sep_wake = is_fp32_storage(b->precision) && ph.wake && !fused_tick(b, ph);
     const Target t = target(b, ph, g);
@@ -755,7 +774,7 @@ int launch_group_tick(vfp_batch *b, const Phase &ph, int g, int parity)
             launch_wake(b, t, parity);
             if (timed) t1 = timing_event(b);
         }
-        launch_step_k<float, WAKE_EXTERNAL>(b, ph, t, parity);
+        launch_step_k<float, WAKE_EXTERNAL>(b, ph, t, parity, rec, mom_done);
     }
     HIPCHK(hipGetLastError());
     if (timed) {
@@ -773,13 +792,17 @@ int launch_group_tick(vfp_batch *b, const Phase &ph, int g, int parity)
 }
 
 // stats over an explicit list of (simulation, buffer) pairs
-int launch_stats(vfp_batch *b, const int *d_which, const int *d_buf, int cnt, int record, hipStream_t st)
+int launch_stats(vfp_batch *b, const int *d_which, const int *d_buf, int cnt, int record, hipStream_t st,
+                 bool have_moments = false)
 {
     if (cnt == 0) return VFP_OK;
-    // per-column sums over 16-column tiles of the largest grid
+    // per-column sums over 16-column tiles of the largest grid (unless the
+    // step that made the state left them)
     const int maxn = (int)(b->lds_stats / (2 * sizeof(double)));
     const dim3 mgrid((unsigned)((maxn + 15) / 16), (unsigned)cnt);
-    if (b->precision == VFP_FP64)
+    if (have_moments)
+        ;
+    else if (b->precision == VFP_FP64)
         hipLaunchKernelGGL(moments_kernel<double>, mgrid, dim3(kThreads), 0, st, b->d_sd, d_which, d_buf);
     else if (b->precision == VFP_FIXED)
         hipLaunchKernelGGL(moments_kernel<int64_t>, mgrid, dim3(kThreads), 0, st, b->d_sd, d_which, d_buf);
@@ -812,11 +835,11 @@ int launch_stats(vfp_batch *b, const int *d_which, const int *d_buf, int cnt, in
 
 // record launch of group g after a tick that read buffer `par`: the group's
 // simulations' fresh states are in buffer par ^ 1
-int launch_record(vfp_batch *b, const Phase &ph, int g, int par)
+int launch_record(vfp_batch *b, const Phase &ph, int g, int par, bool have_moments)
 {
     const Group &gr = ph.grp[g];
     return launch_stats(b, b->d_active + gr.act_off, b->d_buf01 + (par ^ 1) * b->count, (int)gr.act_cnt, 1,
-                        g == 0 ? b->stream : b->xstream[g - 1]);
+                        g == 0 ? b->stream : b->xstream[g - 1], have_moments);
 }
 
 // d_idx[0..count) = all simulations, d_idx[count..2count) = their buffers
@@ -855,8 +878,10 @@ int check_finite(vfp_batch *b, int s)
 // `par`, plus the group's record launch when due
 int enqueue_group_tick(vfp_batch *b, const Phase &ph, int g, int par, int64_t tk)
 {
-    int rc = launch_group_tick(b, ph, g, par);
-    if (rc == VFP_OK && b->every > 0 && ((tk + 1 - b->rec_base) % b->every) == 0) rc = launch_record(b, ph, g, par);
+    const bool rec = b->every > 0 && ((tk + 1 - b->rec_base) % b->every) == 0;
+    bool mom = false;
+    int rc = launch_group_tick(b, ph, g, par, rec, &mom);
+    if (rc == VFP_OK && rec) rc = launch_record(b, ph, g, par, mom);
     return rc;
 }
 

@@ -595,17 +595,24 @@ __global__ __launch_bounds__(kThreads) void moments_kernel(const SimDev *__restr
     for (int c = 0; c < 4; ++c) {
         const int i = blockIdx.x * 16 + c * kWaves + wv;
         if (i >= n) break;
+        // blocks of 256 rows, four consecutive rows per lane, a wave sum per
+        // block, the blocks added in order: the order in which the staged step
+        // kernel forms the same sums when a record row follows it
         double a0 = 0.0, a1 = 0.0, a2 = 0.0;
-        for (int j = lane; j < n; j += 64) {
-            const double v = stored_value(f[(size_t)i * n + j], sd.fixb);
-            const double p = sd.p_min + j * sd.dp;
-            a0 += v;
-            a1 += p * v;
-            a2 += p * p * v;
+        for (int j0 = 0; j0 < n; j0 += 256) {
+            double m0 = 0.0, m1 = 0.0, m2 = 0.0;
+            const int j = j0 + 4 * lane;
+            for (int r = 0; r < 4 && j + r < n; ++r) {
+                const double v = stored_value(f[(size_t)i * n + j + r], sd.fixb);
+                const double pj = fma((double)(j + r), sd.dp, sd.p_min);
+                m0 += v;
+                m1 = fma(pj, v, m1);
+                m2 = fma(pj * pj, v, m2);
+            }
+            a0 += wave_sum(m0);
+            a1 += wave_sum(m1);
+            a2 += wave_sum(m2);
         }
-        a0 = wave_sum(a0);
-        a1 = wave_sum(a1);
-        a2 = wave_sum(a2);
         if (lane == 0) {
             sd.mom[3 * i] = a0;
             sd.mom[3 * i + 1] = a1;

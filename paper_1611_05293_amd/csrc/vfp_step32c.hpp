@@ -158,7 +158,10 @@ __device__ __forceinline__ void kick_damp4(const float *a, const float (&w)[4], 
 
 // One work unit (a strip of whole columns of one simulation): reads buffer
 // `parity`, writes the next state and its FP64 column sums to parity ^ 1.
-template <int K, int WAKE, bool CLAMP, int ROT, bool COH = false>
+// With MOM it also writes the per-column moments sum psi, sum p psi and
+// sum p^2 psi of the new state (FP64, sd.mom), which a record row would
+// otherwise read the whole state again for.
+template <int K, int WAKE, bool CLAMP, int ROT, bool COH = false, bool MOM = false>
 __device__ __forceinline__ void step32c_unit(const SimDev &sd, const Unit &u, int parity)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -447,6 +450,7 @@ __device__ __forceinline__ void step32c_unit(const SimDev &sd, const Unit &u, in
     const float sk1 = sf * sd.fk1;
     const float se0 = sf * sd.fe[0], se1 = sf * sd.fe[1], se2 = sf * sd.fe[2], se3 = sf * sd.fe[3];
     float *Sp = S;     // per-lane partial sums of the outputs, [W][nb][64] (fits: host bound)
+    double *Mp = (double *)(Sp + (size_t)W * nb * 64);   // MOM: per (column, block) moments, [W][nb][3]
     for (int b = b0; b < nb; b += bst) {
         const int j = 256 * b + 4 * lane;
         const bool act = j < n;
@@ -466,6 +470,7 @@ __device__ __forceinline__ void step32c_unit(const SimDev &sd, const Unit &u, in
         }
         for (int c = c0; c < W; c += cst) {
             float part = 0.0f;
+            double m0 = 0.0, m1 = 0.0, m2 = 0.0;
             if (act) {
                 const int km = sh_km[c];
                 const float4 w4 = *(const float4 *)sh_kw[c];
@@ -510,8 +515,27 @@ __device__ __forceinline__ void step32c_unit(const SimDev &sd, const Unit &u, in
                 *(__attribute__((address_space(1))) f32x4 *)(dst + (size_t)(i0 + c) * n + j) =
                     f32x4{o[0], o[1], o[2], o[3]};
                 part = (o[0] + o[1]) + (o[2] + o[3]);
+                if constexpr (MOM) {
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        const double v = (double)o[r], pj = fma((double)(j + r), sd.dp, sd.p_min);
+                        m0 += v;
+                        m1 = fma(pj, v, m1);
+                        m2 = fma(pj * pj, v, m2);
+                    }
+                }
             }
             Sp[(c * nb + b) * 64 + lane] = part;              // the staging buffer is free now
+            if constexpr (MOM) {
+                m0 = wave_sum(m0);
+                m1 = wave_sum(m1);
+                m2 = wave_sum(m2);
+                if (lane == 0) {
+                    Mp[(c * nb + b) * 3] = m0;
+                    Mp[(c * nb + b) * 3 + 1] = m1;
+                    Mp[(c * nb + b) * 3 + 2] = m2;
+                }
+            }
         }
     }
     __syncthreads();
@@ -526,16 +550,25 @@ __device__ __forceinline__ void step32c_unit(const SimDev &sd, const Unit &u, in
         for (int off = g >> 1; off > 0; off >>= 1) t += __shfl_xor(t, off, 64);
         if (c < W && sub == 0) store_cs<COH>(cs_next + i0 + c, t);
     }
+    if constexpr (MOM) {
+        // the column's blocks added in block order
+        if (tid < 3 * W) {
+            const int c = tid / 3, k = tid - 3 * c;
+            double t = 0.0;
+            for (int b = 0; b < nb; ++b) t += Mp[(c * nb + b) * 3 + k];
+            sd.mom[3 * (i0 + c) + k] = t;
+        }
+    }
 }
 
-template <int K, int WAKE, bool CLAMP, int ROT>
+template <int K, int WAKE, bool CLAMP, int ROT, bool MOM = false>
 __global__ __launch_bounds__(kThreads) void step32c_kernel(const SimDev *__restrict__ sims,
                                                            const Unit *__restrict__ units, int nunits,
                                                            int parity)
 {
     const Unit u = units[blockIdx.x];
     if (u.w == 0) return;                     // padding slot
-    step32c_unit<K, WAKE, CLAMP, ROT>(sims[u.sim], u, parity);
+    step32c_unit<K, WAKE, CLAMP, ROT, false, MOM>(sims[u.sim], u, parity);
 }
 
 // Wake kinds of the fused tick: FP32 vector ALU, FP16 or BF16 hi/lo matrix cores.
