@@ -60,6 +60,12 @@ void lds_limit(K kernel, size_t bytes, int &cur)
             cur = (int)bytes;
     }
 }
+// one limit per kernel for every caller (the limit only ever grows)
+void wakev_limit(size_t bytes)
+{
+    static int cur = 0;
+    lds_limit(wakev_kernel, bytes, cur);
+}
 constexpr int kMaxGraphPhases = 8;   // retirement phases that get graphs
 constexpr int kMaxGroups = 4;        // stream groups of a batch
 constexpr int kXcds = 8;             // XCDs of the GPU: the dispatcher deals blocks to them round-robin
@@ -826,7 +832,9 @@ int launch_stats(vfp_batch *b, const int *d_which, const int *d_buf, int cnt, in
     }
     // the wake of every listed simulation over row tiles of the largest grid, then P
     const unsigned tiles = (unsigned)((maxn + 63) / 64);
-    hipLaunchKernelGGL(wakev_kernel, dim3(tiles, (unsigned)cnt), dim3(kThreads), 0, st, b->d_sd, d_which);
+    wakev_limit(wakev_lds(maxn));
+    hipLaunchKernelGGL(wakev_kernel, dim3(tiles, (unsigned)cnt), dim3(kThreads), wakev_lds(maxn), st, b->d_sd,
+                       d_which);
     hipLaunchKernelGGL(power_kernel, dim3(cnt), dim3(kThreads), 0, st, b->d_sd, d_which, b->rec_base,
                        b->every, record);
     HIPCHK(hipGetLastError());
@@ -1025,9 +1033,10 @@ int launch_haissinski(vfp_batch *b, int i, int buf, int iters, double alpha)
     static int cur = 0;
     lds_limit(haissinski_kernel<T>, lds, cur);
     hipLaunchKernelGGL(haissinski_kernel<T>, dim3(1), dim3(kThreads), 0, b->stream, b->d_sd, i, buf, 0, alpha);
+    wakev_limit(wakev_lds(n));
     for (int it = 0; it < iters; ++it) {
-        hipLaunchKernelGGL(wakev_kernel, dim3((unsigned)((n + 63) / 64), 1), dim3(kThreads), 0, b->stream, b->d_sd,
-                           b->d_idx);
+        hipLaunchKernelGGL(wakev_kernel, dim3((unsigned)((n + 63) / 64), 1), dim3(kThreads), wakev_lds(n), b->stream,
+                           b->d_sd, b->d_idx);
         hipLaunchKernelGGL(haissinski_kernel<T>, dim3(1), dim3(kThreads), lds, b->stream, b->d_sd, i, buf, 1, alpha);
     }
     hipLaunchKernelGGL(haissinski_kernel<T>, dim3((unsigned)std::min(n, 1024)), dim3(kThreads), 0, b->stream, b->d_sd,

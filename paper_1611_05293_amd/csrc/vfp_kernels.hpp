@@ -683,28 +683,42 @@ __global__ __launch_bounds__(kThreads) void stats_kernel(const SimDev *__restric
 __global__ __launch_bounds__(kThreads) void wakev_kernel(const SimDev *__restrict__ sims,
                                                          const int *__restrict__ which)
 {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
     __shared__ double part[kWaves][64];
     const SimDev &sd = sims[which[blockIdx.y]];
-    const int n = sd.n, lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int n = sd.n, tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const int i0 = blockIdx.x * 64;
     if (i0 >= n) return;
+    // rho and the tile's lag window in LDS: lw[k] = w[i0 - (n - 1) + k], so that
+    // w[i - j] = lw[i - i0 + n - 1 - j] (dynamic LDS: (2 n + 63) doubles at most)
+    double *rho = (double *)smem_raw;
+    double *lw = rho + n;
+    if (sd.has_wake) {
+        const int nl = min(n + 63, 2 * n - 1 - i0);
+        for (int k = tid; k < n; k += kThreads) rho[k] = sd.rho_out[k];
+        for (int k = tid; k < nl; k += kThreads) lw[k] = sd.wl64[i0 + k];
+    }
+    __syncthreads();
     const int i = i0 + lane;
     double v = 0.0;
     if (sd.has_wake && i < n) {
-        const double *wi = sd.wl64 + i + n - 1;          // wi[-j] = w[i - j]
+        const double *wi = lw + lane + n - 1;            // wi[-j] = w[i - j]
         double v0 = 0.0, v1 = 0.0;
         int j = wv;
         for (; j + kWaves < n; j += 2 * kWaves) {
-            v0 = fma(wi[-j], sd.rho_out[j], v0);
-            v1 = fma(wi[-j - kWaves], sd.rho_out[j + kWaves], v1);
+            v0 = fma(wi[-j], rho[j], v0);
+            v1 = fma(wi[-j - kWaves], rho[j + kWaves], v1);
         }
-        if (j < n) v0 = fma(wi[-j], sd.rho_out[j], v0);
+        if (j < n) v0 = fma(wi[-j], rho[j], v0);
         v = v0 + v1;
     }
     part[wv][lane] = v;
     __syncthreads();
     if (wv == 0 && i < n) sd.v_out[i] = sd.has_wake ? sd.S * ((part[0][lane] + part[1][lane]) + (part[2][lane] + part[3][lane])) : 0.0;
 }
+
+// dynamic LDS of wakev_kernel for grids of at most n points
+__host__ __device__ inline size_t wakev_lds(int n) { return (size_t)(2 * n + 63) * sizeof(double); }
 
 // P = sum_i rho_i V_i, the non-finite flag, and the record row
 __global__ __launch_bounds__(kThreads) void power_kernel(const SimDev *__restrict__ sims,
