@@ -257,3 +257,32 @@ def test_tick_forms_groups_graphs_and_records_agree(precision):
         for i in range(len(sims)):
             assert np.array_equal(psis[i], out[0][0][i])
             assert np.array_equal(recs[i], out[0][1][i])
+
+
+@pytest.mark.parametrize("precision", ["fp32", "fp16"])
+@pytest.mark.parametrize("rotation", [0, 1])
+def test_record_rows_after_staged_ticks_match_oracle_series(precision, rotation):
+    """Record rows after split ticks of the staged kernel take the per-column
+    moments that the step launch itself leaves (no second pass over psi;
+    Sec. IV.C: bunch length, energy spread and CSR power as time series).
+    Every row agrees with the FP64 oracle's series to the accuracy of the
+    FP32 state: the step counts exactly, Q, <q>, sigma_q, <p>, sigma_p to
+    2e-5 of their scale and P to 1e-4 of max |P|."""
+    sims = [small_sim(n=32, steps=80, S=0.4, Pi=0.5, seed=1, rotation=rotation),
+            small_sim(n=48, steps=120, S=1.2, Pi=1.0, seed=2, rotation=rotation),
+            small_sim(n=100, steps=250, S=0.9, Pi=0.8, seed=4, lo=-8.0, hi=8.0, rotation=rotation)]
+    b = vfp.Batch([vfp.sim_kwargs(s, precision=precision) for s in sims])
+    b.set_tuning(0, True, 1)
+    b.set_streams(2)
+    b.record(5, 20)
+    b.step(40)
+    for i, s in enumerate(sims):
+        _, rec, _, _ = oracle_run(s, 40, every=5)
+        r = b.read_record(i)
+        assert r.shape == rec.shape == (8, 7)
+        assert np.array_equal(r[:, 0], rec[:, 0])
+        for k in range(1, 6):
+            scale = max(np.abs(rec[:, k]).max(), 1.0)
+            assert np.abs(r[:, k] - rec[:, k]).max() <= 2e-5 * scale, (i, k)
+        assert np.abs(r[:, 6] - rec[:, 6]).max() <= 1e-4 * np.abs(rec[:, 6]).max(), i
+    b.close()
