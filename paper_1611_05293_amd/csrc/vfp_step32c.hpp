@@ -395,16 +395,28 @@ __device__ __forceinline__ void step32c_unit(const SimDev &sd, const Unit &u, in
                 const int fl = cvt_floor(sh);
                 float l[K];
                 lagrange_fma<K>(__builtin_amdgcn_fractf(sh), l);
+                // the shift is the row's, so the K taps slide by one staged column per
+                // output column: slot (c + k) % K holds tap k of output column c
                 const float *col = S + (hl + fl - o0) * SY + y;
-                for (int c = 0; c < W; ++c, col += SY) {
-                    float f[K];
+                float fw[K];
 #pragma unroll
-                    for (int k = 0; k < K; ++k) f[k] = col[k * SY];
-                    float v = l[0] * f[0];
+                for (int k = 0; k < K - 1; ++k) fw[k] = col[k * SY];
+                for (int c0 = 0; c0 < W; c0 += K) {
 #pragma unroll
-                    for (int k = 1; k < K; ++k) v = fmaf(l[k], f[k], v);
-                    if constexpr (CLAMP) v = fminf(fmaxf(v, fminf(f[o0], f[o0 + 1])), fmaxf(f[o0], f[o0 + 1]));
-                    Dm[c * SY + y] = v;
+                    for (int u = 0; u < K; ++u) {
+                        const int c = c0 + u;
+                        if (c < W) {
+                            fw[(u + K - 1) % K] = col[(c + K - 1) * SY];
+                            float f[K];
+#pragma unroll
+                            for (int k = 0; k < K; ++k) f[k] = fw[(u + k) % K];
+                            float v = l[0] * f[0];
+#pragma unroll
+                            for (int k = 1; k < K; ++k) v = fmaf(l[k], f[k], v);
+                            if constexpr (CLAMP) v = fminf(fmaxf(v, fminf(f[o0], f[o0 + 1])), fmaxf(f[o0], f[o0 + 1]));
+                            Dm[c * SY + y] = v;
+                        }
+                    }
                 }
             }
             __syncthreads();
