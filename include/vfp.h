@@ -224,10 +224,10 @@ const char *vfp_last_error(void);
 /* One tick advances every active simulation by one of its own steps.  The */
 /* FP32-storage forms (VFP_FP32 and the mixed forms) run one of two tick   */
 /* forms (vfp_batch_set_tuning): split, a wake launch then the fused step  */
-/* launch; or fused, ONE launch in which every work unit steps its strip   */
-/* with the wake the previous tick left and wake tiles placed after the    */
-/* units compute each simulation's next wake once its units are done (the */
-/* first tick after a state change is preceded by one wake launch).        */
+/* launch; or fused, ONE launch per tick whose wake tiles (first in the    */
+/* launch) compute each simulation's wake while its work units stage and   */
+/* rotate their strips; a unit waits for its simulation's tiles only      */
+/* before it kicks.                                                        */
 /* VFP_FP64 and VFP_FIXED compute the wake slice of each strip inside      */
 /* their one step launch.  The simulations are split in stream groups     */
 /* (vfp_batch_set_streams) whose launches overlap.  Ticks are replayed     */

@@ -292,9 +292,8 @@ struct vfp_batch {
     int *d_active = nullptr;
     WakeTile *d_wtiles = nullptr;
     size_t units_cap = 0, items_cap = 0, actv_cap = 0, wtiles_cap = 0;
-    unsigned *d_done = nullptr;    // fused tick: [2][count] finished units per simulation and tick parity
-    int *d_flag = nullptr;         // fused tick: set when a wake tile's wait exceeded its bound
-    bool wake_valid = false;       // vext/sext[parity] hold the wake of every active simulation's current state
+    unsigned *d_done = nullptr;    // fused tick: [2][count] finished wake tiles per simulation and tick parity
+    int *d_flag = nullptr;         // fused tick: set when a unit's wait for its wake exceeded its bound
     int *d_idx = nullptr;          // scratch index arrays for per-call kernels (2*count)
     int *d_buf01 = nullptr;        // count zeros then count ones: buffer tables for records
     int64_t tick = 0;              // ticks since create
@@ -401,28 +400,25 @@ void lay_out_units(vfp_batch *b, std::vector<int> sims, std::vector<Unit> &out)
         for (int x = 0; x < kXcds; ++x) out.push_back(k < xcd[x].size() ? xcd[x][k] : Unit{0, 0, 0, 0});
 }
 
-// Item list of the fused tick for one group: its units in dispatch order,
-// then each simulation's wake tiles (w = -1, tile index in i0) in whole rounds
-// of kXcds slots.  A wake tile waits for its simulation's units, which all
-// come before it.  (Wake tiles placed between the units, about one round of
-// resident blocks after their simulation's last unit, measured slower on the
-// 200-simulation scan: 119 against 112 us per tick.)
+// Item list of the fused tick for one group: each simulation's wake tiles
+// (w = -1, tile index in i0) first, padded to whole rounds of kXcds slots so
+// that the units keep their XCD placement, then the group's units in
+// dispatch order with nu = their simulation's wake tile count.  A unit waits
+// only for its simulation's tiles, which all come before it and wait for
+// nothing.
 void lay_out_items(vfp_batch *b, const Group &g)
 {
-    std::vector<int> nu(b->count, 0);
-    for (size_t k = g.unit_off; k < g.unit_off + g.unit_cnt; ++k)
-        if (b->units[k].w > 0) nu[b->units[k].sim] = b->units[k].nu;
-    b->items.insert(b->items.end(), b->units.begin() + g.unit_off, b->units.begin() + g.unit_off + g.unit_cnt);
-    size_t t = g.tile_off;
-    while (t < g.tile_off + g.tile_cnt) {
-        for (int x = 0; x < kXcds; ++x, ++t) {
-            if (t < g.tile_off + g.tile_cnt) {
-                const WakeTile &w = b->wtiles[t];
-                b->items.push_back(Unit{w.sim, w.tile, -1, nu[w.sim]});
-            } else {
-                b->items.push_back(Unit{0, 0, 0, 0});
-            }
-        }
+    std::vector<int> nt(b->count, 0);
+    for (size_t t = g.tile_off; t < g.tile_off + g.tile_cnt; ++t) {
+        const WakeTile &w = b->wtiles[t];
+        b->items.push_back(Unit{w.sim, w.tile, -1, 0});
+        ++nt[w.sim];
+    }
+    while (b->items.size() % kXcds) b->items.push_back(Unit{0, 0, 0, 0});
+    for (size_t k = g.unit_off; k < g.unit_off + g.unit_cnt; ++k) {
+        Unit u = b->units[k];
+        if (u.w > 0) u.nu = nt[u.sim];
+        b->items.push_back(u);
     }
 }
 
@@ -578,7 +574,6 @@ int rebuild(vfp_batch *b)
             ph.graphs = true;
         }
     }
-    b->wake_valid = false;
     return VFP_OK;
 }
 
@@ -877,7 +872,7 @@ int check_finite(vfp_batch *b, int s)
     int late = 0;
     HIPCHK(hipMemcpy(&bad, (double *)(b->arena + b->hs[s].off_stat) + 7, sizeof(double), hipMemcpyDeviceToHost));
     HIPCHK(hipMemcpy(&late, b->d_flag, sizeof(int), hipMemcpyDeviceToHost));
-    if (late != 0) return fail(VFP_EDEVICE, "a wake tile's wait for its simulation's units exceeded its bound");
+    if (late != 0) return fail(VFP_EDEVICE, "a unit's wait for its simulation's wake tiles exceeded its bound");
     if (bad != 0.0) return fail(VFP_EDEVICE, "non-finite density or wake detected");
     return VFP_OK;
 }
@@ -924,14 +919,6 @@ int capture_graph(vfp_batch *b, Phase &ph, int g, int par)
     return VFP_OK;
 }
 
-// the first fused tick after a state change needs the wake of the current state
-int prime_wake(vfp_batch *b, const Phase &ph)
-{
-    int rc = fork_streams(b, ph);
-    for (int g = 0; g < ph.ngroups && rc == VFP_OK; ++g) launch_wake(b, target(b, ph, g), b->parity);
-    if (rc == VFP_OK) HIPCHK(hipGetLastError());
-    return rc;
-}
 
 // Enqueue nticks ticks: graph replays where a whole graph fits before the
 // next retirement (and starts on the record cadence), single ticks otherwise;
@@ -947,14 +934,8 @@ int advance(vfp_batch *b, int64_t nticks)
         Phase &ph = b->phases[b->cur];
         if (ph.active.empty()) break;                  // every simulation has retired
         const int64_t until = std::min(nticks, ph.end - b->tick);
-        const bool fused = fused_tick(b, ph);
         int64_t done = 0;
         while (done < until) {
-            if (fused && !b->wake_valid) {
-                rc = prime_wake(b, ph);                // the wake of the current state, once
-                if (rc) break;
-                b->wake_valid = true;
-            }
             const int64_t left = until - done;
             const bool aligned = b->every == 0 || ((b->tick - b->rec_base) % b->every) == 0;
             if (ph.graphs && !b->timing && left >= b->G && aligned) {
@@ -973,8 +954,6 @@ int advance(vfp_batch *b, int64_t nticks)
                 ++b->tick;
                 ++done;
             }
-            // a fused tick leaves the next tick's wake; the other forms do not rely on it
-            b->wake_valid = fused;
         }
         for (int s : ph.active) b->hs[s].steps += done;
         nticks -= done;
@@ -1119,7 +1098,6 @@ int upload_psi(vfp_batch *b, int s, const double *psi, bool gaussian)
             return fail(VFP_EINVAL, "initial density must have a positive, finite charge");
         b->sd[s].Q0 = Q0;
         b->sd[s].step0 = b->tick;
-        b->wake_valid = false;
         return upload_sims(b);
     }
     // Q0 = dq*dp*sum(psi0) of the FP64 input (stat[0] is scratch here)
@@ -1133,7 +1111,6 @@ int upload_psi(vfp_batch *b, int s, const double *psi, bool gaussian)
     if (!(Q0 > 0.0) || !std::isfinite(Q0)) return fail(VFP_EINVAL, "initial density must have a positive, finite charge");
     b->sd[s].Q0 = Q0;
     b->sd[s].step0 = b->tick;
-    b->wake_valid = false;
     return upload_sims(b);
 }
 
@@ -1950,7 +1927,6 @@ int vfp_batch_autotune(vfp_batch *b, int32_t ticks, int32_t *chosen_cells, int32
             // a phase shorter than the trial is stepped past its end: only the time counts
             const Phase &ph = b->phases[0];
             if (ph.active.empty()) break;
-            if (fused_tick(b, ph)) rc = prime_wake(b, ph);
             for (int t = 0; t < 2 + ticks && rc == VFP_OK; ++t) {
                 if (t == 2) {
                     rc = join_streams(b);

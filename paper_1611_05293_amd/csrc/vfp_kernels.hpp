@@ -161,6 +161,21 @@ __device__ __forceinline__ void store_cs(double *p, double v)
 }
 __device__ __forceinline__ void wait_stores() { __builtin_amdgcn_s_waitcnt(0x0F70); }   // s_waitcnt vmcnt(0)
 
+// stores of the wake (V, s) that workgroups of the same launch read: written
+// through to the level coherent across the XCDs when OUTCOH
+template <bool OUTCOH>
+__device__ __forceinline__ void store_wake_f(float *p, float v)
+{
+    if constexpr (OUTCOH) __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    else *p = v;
+}
+template <bool OUTCOH>
+__device__ __forceinline__ void store_wake_d(double *p, double v)
+{
+    if constexpr (OUTCOH) __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    else *p = v;
+}
+
 // Work units of a step launch: the host lays them out in dispatch order
 // (block k*8 + x runs on XCD x), so block b takes units[b]; slots with
 // w == 0 are padding and their blocks return at once, before any barrier.
@@ -882,7 +897,7 @@ __host__ __device__ inline size_t wake_mfma_lds(int n)
 // buffer `parity`; writes V (vext[parity]) for the tile's rows and, for tile
 // 0, the factor s the wake was made with (sext[parity]).  All LDS is the
 // dynamic buffer.
-template <bool FP16, bool COH = false>
+template <bool FP16, bool COH = false, bool OUTCOH = false>
 __device__ void wake_mfma_tile(const SimDev &sd, int tile, int parity)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -1012,9 +1027,9 @@ __device__ void wake_mfma_tile(const SimDev &sd, int tile, int parity)
             double v = t[q];
             for (int k = 0; k < kWaves - 1; ++k) v += wsum[(k * 64 + lane) * 4 + q];
             const int i = 16 * (I0 + a) + kq + q;
-            if (i < n) sd.vext[parity * n + i] = (float)(v * outscale);
+            if (i < n) store_wake_f<OUTCOH>(sd.vext + parity * n + i, (float)(v * outscale));
         }
-        if (tile == 0 && lane == 0) sd.sext[parity] = s;
+        if (tile == 0 && lane == 0) store_wake_d<OUTCOH>(sd.sext + parity, s);
     }
 }
 
@@ -1037,7 +1052,7 @@ __global__ __launch_bounds__(kThreads) void wake_mfma2_kernel(const SimDev *__re
 __host__ __device__ inline size_t wake_vec_head(int n) { return ((size_t)(2 * n + 255) * sizeof(float) + 15) & ~(size_t)15; }
 __host__ __device__ inline size_t wake_vec_lds(int n) { return wake_vec_head(n) + kWaves * sizeof(double); }
 
-template <bool COH = false>
+template <bool COH = false, bool OUTCOH = false>
 __device__ void wake_vec_tile(const SimDev &sd, int tile, int parity)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -1084,9 +1099,9 @@ __device__ void wake_vec_tile(const SimDev &sd, int tile, int parity)
             for (int j = jb; j < je; ++j) a32 = fmaf(lw[-j], rho[j], a32);
             acc += a32;
         }
-        sd.vext[parity * n + i] = (float)(sd.S * s * acc);
+        store_wake_f<OUTCOH>(sd.vext + parity * n + i, (float)(sd.S * s * acc));
     }
-    if (tile == 0 && tid == 0) sd.sext[parity] = s;
+    if (tile == 0 && tid == 0) store_wake_d<OUTCOH>(sd.sext + parity, s);
 }
 
 __global__ __launch_bounds__(kThreads) void wake_vec_kernel(const SimDev *__restrict__ sims,

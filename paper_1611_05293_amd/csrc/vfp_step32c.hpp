@@ -70,6 +70,8 @@ __device__ __forceinline__ void lagrange_fma(float t, float *l)
 __host__ __device__ constexpr int chunk_rows_c(int rot) { return rot == 1 ? 192 : 256; }
 __host__ __device__ constexpr int staged_rows_c(int rot) { return chunk_rows_c(rot) + 8; }
 constexpr int kPF4 = 4;           // staged columns per wave held in registers across a chunk
+// polls of a bounded wait for other workgroups of the same launch (about a second)
+constexpr unsigned kWakeSpinLimit = 1u << 20;
 constexpr int kMaxStripC = 64;    // columns per work unit in this layout
 
 __device__ __forceinline__ int cvt_floor(float x)
@@ -161,8 +163,13 @@ __device__ __forceinline__ void kick_damp4(const float *a, const float (&w)[4], 
 // With MOM it also writes the per-column moments sum psi, sum p psi and
 // sum p^2 psi of the new state (FP64, sd.mom), which a record row would
 // otherwise read the whole state again for.
-template <int K, int WAKE, bool CLAMP, int ROT, bool COH = false, bool MOM = false>
-__device__ __forceinline__ void step32c_unit(const SimDev &sd, const Unit &u, int parity)
+// With WAITW (the one-launch tick) the wake of the state is made in the same
+// launch: the unit rotates first, then waits until the simulation's nt wake
+// tiles have counted themselves in *rdy (a bounded wait; *flag reports one
+// that ran out), and only then reads V and s and forms its kick weights.
+template <int K, int WAKE, bool CLAMP, int ROT, bool COH = false, bool MOM = false, bool WAITW = false>
+__device__ __forceinline__ void step32c_unit(const SimDev &sd, const Unit &u, int parity,
+                                             const unsigned *rdy = nullptr, int nt = 0, int *flag = nullptr)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     __shared__ double red[kThreads];
@@ -239,8 +246,10 @@ __device__ __forceinline__ void step32c_unit(const SimDev &sd, const Unit &u, in
     load_cols(0, 0);
 
     // ---- prologue: renormalisation factor, wake slice, kick weights, pads
-    double s;
-    if constexpr (WAKE == WAKE_EXTERNAL) {
+    double s = 1.0;
+    if constexpr (WAITW) {
+        static_assert(WAKE == WAKE_EXTERNAL, "the one-launch tick reads the wake of its own launch");
+    } else if constexpr (WAKE == WAKE_EXTERNAL) {
         s = sd.sext[parity];
     } else {
         double part = 0.0;
@@ -283,18 +292,22 @@ __device__ __forceinline__ void step32c_unit(const SimDev &sd, const Unit &u, in
             shift = sd.S * s * v * sd.kick;
             sd.vext[parity * n + i0 + tid] = (float)(sd.S * s * v);      // the wake this step used
         }
-    } else if constexpr (WAKE == WAKE_EXTERNAL) {
+    } else if constexpr (WAKE == WAKE_EXTERNAL && !WAITW) {
         if (tid < W) shift = (double)sd.vext[parity * n + i0 + tid] * sd.kick;
     }
-    if (tid < W) {
-        const double ic = (double)(i0 + tid);
-        sh_xy[tid] = make_float2((float)fma(ic, sd.axi, sd.ax0), (float)fma(ic, sd.cyi, sd.cy0));
-        const double fl = floor(shift);
+    // kick weights of column tid from its shift in rows
+    auto kick_weights = [&](double sh) {
+        const double fl = floor(sh);
         float l[K];
-        lagrange_fma<K>((float)(shift - fl), l);
+        lagrange_fma<K>((float)(sh - fl), l);
         for (int k = 0; k < K; ++k) sh_kw[tid][k] = l[k];
         for (int k = K; k < 4; ++k) sh_kw[tid][k] = 0.0f;
         sh_km[tid] = (int)fmax(fmin(fl, 1.0e6), -1.0e6);
+    };
+    if (tid < W) {
+        const double ic = (double)(i0 + tid);
+        sh_xy[tid] = make_float2((float)fma(ic, sd.axi, sd.ax0), (float)fma(ic, sd.cyi, sd.cy0));
+        if constexpr (!WAITW) kick_weights(shift);
     }
     if constexpr (ROT == 1) {
         // RF kick of column i pulls along p from p + dtheta*q_i: shift tk*(q_min/dq + i) rows
@@ -445,6 +458,24 @@ __device__ __forceinline__ void step32c_unit(const SimDev &sd, const Unit &u, in
         }
     }
     __syncthreads();
+    if constexpr (WAITW) {
+        if (tid == 0 && __hip_atomic_load(flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0) {
+            unsigned spins = 0;
+            while (__hip_atomic_load(rdy, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < (unsigned)nt) {
+                if (++spins == kWakeSpinLimit) {
+                    __hip_atomic_store(flag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    break;
+                }
+                __builtin_amdgcn_s_sleep(1);
+            }
+        }
+        __syncthreads();
+        s = __hip_atomic_load(sd.sext + parity, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (tid < W)
+            kick_weights((double)__hip_atomic_load(sd.vext + parity * n + i0 + tid, __ATOMIC_RELAXED,
+                                                   __HIP_MEMORY_SCOPE_AGENT) * sd.kick);
+        __syncthreads();
+    }
 
     // ---- kick and damping/diffusion.  Output row j uses the kicked values of
     // rows j-1 .. j+2 with coefficients s*(e_k + ku_j*d_k), ku_j = k1*p_j/dp,
@@ -586,58 +617,43 @@ __global__ __launch_bounds__(kThreads) void step32c_kernel(const SimDev *__restr
 // Wake kinds of the fused tick: FP32 vector ALU, FP16 or BF16 hi/lo matrix cores.
 enum TickWake { TW_VEC = 0, TW_FP16 = 1, TW_BF16 = 2 };
 
-// One tick of a batch in one launch.  The grid walks one list of items:
-// work units (w > 0), empty slots (w == 0) and wake tiles (w < 0, tile index
-// in i0).  Every unit steps its strip with the wake V_t and factor s_t of its
-// simulation's current state (vext/sext[parity]), stores its column sums
-// coherently, waits for those stores and counts itself done in
-// done[parity][sim] (no value returned, so the unit's block ends at once).  A
-// wake tile waits until every unit of its simulation has counted itself, then
-// computes its part of V_{t+1} and s_{t+1} from the fresh column sums (Sec.
-// II.B, Eq. "wakepotential": the profile the next step's kick uses) and
-// clears the previous tick's counter done[parity^1][sim].  The host places
-// the wake tiles after all units in the list, so every item a wake tile waits
-// for comes before it and its wait ends once those blocks have run (the tiles
-// are fewer than the resident slots); a wait longer than kWakeSpinLimit polls
-// (about a second, far beyond any tick) sets *flag instead, reported by the
-// host as a device error, and once it is set no wake tile waits any more, so
-// every launch finishes.
-constexpr unsigned kWakeSpinLimit = 1u << 20;
-
+// One tick of a batch in one launch.  The grid walks one list of items: the
+// wake tiles of every simulation first (w < 0, tile index in i0), then the
+// work units (w > 0, nu = the simulation's wake tile count), with empty
+// slots (w == 0) between the two parts.  A wake tile computes its part of
+// the wake V_t and the factor s_t of the current state from its column sums
+// (made by the previous launch; Sec. II.B, Eq. "wakepotential"), stores them
+// through to the coherent level, waits for the stores and counts itself in
+// ready[parity][sim]; tile 0 also clears the previous launch's counter
+// ready[parity^1][sim] for the launch after this one.  A unit stages and
+// rotates its strip, which needs no wake, and only then waits for its
+// simulation's tiles and kicks.  Tiles wait for nothing and come first in
+// the list, so every wait ends once they have run; a wait longer than
+// kWakeSpinLimit polls (about a second, far beyond any tick) sets *flag
+// instead, reported by the host as a device error, and once it is set no unit
+// waits any more, so every launch finishes.
 template <int K, bool CLAMP, int ROT, int WK>
 __global__ __launch_bounds__(kThreads) void tick32_kernel(const SimDev *__restrict__ sims,
                                                           const Unit *__restrict__ items, int nitems, int parity,
-                                                          unsigned *__restrict__ done, int count,
+                                                          unsigned *__restrict__ ready, int count,
                                                           int *__restrict__ flag)
 {
     const Unit u = items[blockIdx.x];
     if (u.w == 0) return;                     // empty slot
     const SimDev &sd = sims[u.sim];
     if (u.w > 0) {
-        step32c_unit<K, WAKE_EXTERNAL, CLAMP, ROT, true>(sd, u, parity);
-        wait_stores();                        // this wave's column sums have reached the coherent level
-        __syncthreads();
-        if (threadIdx.x == 0)
-            (void)__hip_atomic_fetch_add(done + parity * count + u.sim, 1u, __ATOMIC_RELAXED,
-                                         __HIP_MEMORY_SCOPE_AGENT);
+        step32c_unit<K, WAKE_EXTERNAL, CLAMP, ROT, false, false, true>(sd, u, parity, ready + parity * count + u.sim,
+                                                                      u.nu, flag);
         return;
     }
-    if (threadIdx.x == 0 && __hip_atomic_load(flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0) {
-        const unsigned *c = done + parity * count + u.sim;
-        unsigned spins = 0;
-        while (__hip_atomic_load(c, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < (unsigned)u.nu) {
-            if (++spins == kWakeSpinLimit) {
-                __hip_atomic_store(flag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                break;
-            }
-            __builtin_amdgcn_s_sleep(1);
-        }
-    }
+    if (u.i0 == 0 && threadIdx.x == 0)
+        __hip_atomic_store(ready + (parity ^ 1) * count + u.sim, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if constexpr (WK == TW_VEC) wake_vec_tile<false, true>(sd, u.i0, parity);
+    else wake_mfma_tile<WK == TW_FP16, false, true>(sd, u.i0, parity);
+    wait_stores();                            // this wave's V and s have reached the coherent level
     __syncthreads();
-    if constexpr (WK == TW_VEC) wake_vec_tile<true>(sd, u.i0, parity ^ 1);
-    else wake_mfma_tile<WK == TW_FP16, true>(sd, u.i0, parity ^ 1);
     if (threadIdx.x == 0)
-        __hip_atomic_store(done + (parity ^ 1) * count + u.sim, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        (void)__hip_atomic_fetch_add(ready + parity * count + u.sim, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 }  // namespace vfp
