@@ -23,11 +23,12 @@ METRIC = "phase-space cell-updates/s (N²·steps·sims/s), batched vs plain, at 
 HBM_PEAK_GBS = 8000.0
 # the step kernel of each tick form: 0 the generic kernel (also FP64 and fixed
 # point), 1 the LDS-staged step after its own wake launch (split tick), 2 the
-# one-launch tick (LDS-staged step plus the next wake in the same launch)
+# one-launch tick (the wake tiles of the current state, then the LDS-staged
+# step units, in the same launch)
 STEP_KERNEL = {0: "vfp::step_kernel", 1: "vfp::step32c_kernel", 2: "vfp::tick32_kernel"}
 TICK_FORM = {0: "a wake launch (FP32 storage) and a step launch of the generic kernel per group",
              1: "a wake launch then one fused step launch per stream group (split tick)",
-             2: "one launch per stream group: the fused step and the next wake (one-launch tick)"}
+             2: "one launch per stream group: the wake tiles, then the fused step units (one-launch tick)"}
 TRAFFIC_FILE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles",
                             "step_kernel_hbm_traffic_scan200_fp16.json")
 

@@ -271,7 +271,9 @@ int vfp_batch_get_raw(vfp_batch *b, int32_t i, void *out, double *s);
  * kernel does not take (n % 4 != 0, rotation source more than 2 cells away)
  * use the generic kernel either way.  A new batch uses cells_per_unit 8192
  * (1024 for VFP_FP64 and 2048 for VFP_FIXED, whose strips take 16 bytes per
- * cell of LDS), graph replay and staged = 1; 0 restores the default cells.
+ * cell of LDS), graph replay, and staged = 2 for batches of at most 2 Mi
+ * cells per tick (a separate wake launch would sit on the tick's critical
+ * path) or staged = 1 above; 0 restores the default cells.
  * Synchronises the stream and prepares the work layout. */
 int vfp_batch_set_tuning(vfp_batch *b, int32_t cells_per_unit, int32_t use_graph, int32_t staged);
 

@@ -283,9 +283,12 @@ class Batch:
         _check(load().vfp_batch_steps_done(self._h, i, C.byref(v)))
         return v.value
 
-    def set_tuning(self, cells_per_unit: int = 0, use_graph: bool = True, staged: int = 1):
+    def set_tuning(self, cells_per_unit: int = 0, use_graph: bool = True, staged: int | None = None):
         """staged: 0 the generic kernel, 1 the LDS-staged kernel with a wake
-        launch per tick (split), 2 the LDS-staged kernel with the one-launch tick (fused)."""
+        launch per tick (split), 2 the LDS-staged kernel with the one-launch tick
+        (fused); None keeps the current form."""
+        if staged is None:
+            staged = self.get_tuning()[2]
         _check(load().vfp_batch_set_tuning(self._h, int(cells_per_unit), int(bool(use_graph)), int(staged)))
 
     def set_streams(self, groups: int):
