@@ -554,6 +554,16 @@ int rebuild(vfp_batch *b)
     // counters of the fused tick start from zero in every new layout (a revived
     // simulation may have left its last tick's count behind)
     HIPCHK(hipMemsetAsync(b->d_done, 0, sizeof(unsigned) * 2 * b->count, b->stream));
+    for (std::vector<Unit> *v : {&b->units, &b->items})
+        for (Unit &u : *v)
+            if (u.w > 0) {
+                const SimDev &d = b->sd[u.sim];
+                u.n = d.n;
+                u.hl = d.hl;
+                u.hr = d.hr;
+                u.psi[0] = d.psi[0];
+                u.psi[1] = d.psi[1];
+            }
     int rc = upload_vec(b, b->d_units, b->units_cap, b->units);
     if (rc == VFP_OK) rc = upload_vec(b, b->d_items, b->items_cap, b->items);
     if (rc == VFP_OK) rc = upload_vec(b, b->d_active, b->actv_cap, b->actv);

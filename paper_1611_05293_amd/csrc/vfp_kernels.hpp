@@ -71,6 +71,10 @@ struct SimDev {
 struct Unit {
     int32_t sim, i0, w;
     int32_t nu;
+    // copies of the simulation's grid size, halo widths and density buffers,
+    // so that a staged unit can issue its first loads before its SimDev arrives
+    int32_t n, hl, hr, pad;
+    const void *psi[2];
 };
 
 // ---------------------------------------------------------------- helpers

@@ -180,18 +180,18 @@ __device__ __forceinline__ void step32c_unit(const SimDev &sd, const Unit &u, in
     __shared__ float2 sh_xy[kMaxStripC + 3];   // per column: ax0 + i*axi, cy0 + i*cyi (read in groups of K)
     constexpr int o0 = (K - 1) / 2;
 
-    const int n = sd.n, W = u.w, i0 = u.i0, tid = threadIdx.x, lane = tid & 63;
+    const int n = u.n, W = u.w, i0 = u.i0, tid = threadIdx.x, lane = tid & 63;
     const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int LA = n + 2 * kPad;
     constexpr int CH = chunk_rows_c(ROT), SY = staged_rows_c(ROT), Q4 = SY / 4;
-    const int hl = sd.hl, SX = W + hl + sd.hr;
+    const int hl = u.hl, SX = W + hl + u.hr;
     float *A = (float *)smem_raw;
     float *S = A + (size_t)W * LA;
     float *Dm = S + (size_t)SX * SY;
-    const float *__restrict__ src = (const float *)sd.psi[parity];
+    const float *__restrict__ src = (const float *)(parity ? u.psi[1] : u.psi[0]);
     // global address space for the stores, so they are global (not flat) stores
     typedef __attribute__((address_space(1))) float gfloat;
-    gfloat *__restrict__ dst = (gfloat *)sd.psi[parity ^ 1];
+    gfloat *__restrict__ dst = (gfloat *)(parity ? u.psi[0] : u.psi[1]);
     const double *__restrict__ cs = sd.colsum[parity];
     double *__restrict__ cs_next = sd.colsum[parity ^ 1];
 
@@ -610,6 +610,8 @@ __global__ __launch_bounds__(kThreads) void step32c_kernel(const SimDev *__restr
                                                            int parity)
 {
     const Unit u = units[blockIdx.x];
+    // every field of the unit in one round trip, ahead of the padding test
+    asm volatile("" ::"s"(u.sim), "s"(u.n), "s"(u.hl), "s"(u.hr), "s"(u.psi[0]), "s"(u.psi[1]), "s"(parity));
     if (u.w == 0) return;                     // padding slot
     step32c_unit<K, WAKE, CLAMP, ROT, false, MOM>(sims[u.sim], u, parity);
 }
@@ -639,6 +641,8 @@ __global__ __launch_bounds__(kThreads) void tick32_kernel(const SimDev *__restri
                                                           int *__restrict__ flag)
 {
     const Unit u = items[blockIdx.x];
+    // every field of the item in one round trip, ahead of the tests
+    asm volatile("" ::"s"(u.sim), "s"(u.n), "s"(u.hl), "s"(u.hr), "s"(u.psi[0]), "s"(u.psi[1]), "s"(parity));
     if (u.w == 0) return;                     // empty slot
     const SimDev &sd = sims[u.sim];
     if (u.w > 0) {
