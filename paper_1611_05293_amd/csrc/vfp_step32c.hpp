@@ -250,7 +250,7 @@ __device__ __forceinline__ void step32c_unit(const SimDev &sd, const Unit &u, in
     if constexpr (WAITW) {
         static_assert(WAKE == WAKE_EXTERNAL, "the one-launch tick reads the wake of its own launch");
     } else if constexpr (WAKE == WAKE_EXTERNAL) {
-        s = sd.sext[parity];
+        s = ((const __attribute__((address_space(1))) double *)sd.sext)[parity];   // a global (not flat) load
     } else {
         double part = 0.0;
         for (int k = tid; k < n; k += kThreads) part += cs[k];
@@ -292,9 +292,13 @@ __device__ __forceinline__ void step32c_unit(const SimDev &sd, const Unit &u, in
             shift = sd.S * s * v * sd.kick;
             sd.vext[parity * n + i0 + tid] = (float)(sd.S * s * v);      // the wake this step used
         }
-    } else if constexpr (WAKE == WAKE_EXTERNAL && !WAITW) {
-        if (tid < W) shift = (double)sd.vext[parity * n + i0 + tid] * sd.kick;
     }
+    // the wake of an external-wake step: loaded here by every thread (no branch
+    // around the load), used only once the strip is rotated, so that its
+    // latency stays off the prologue
+    float vcol = 0.0f;
+    if constexpr (WAKE == WAKE_EXTERNAL && !WAITW)
+        vcol = ((const __attribute__((address_space(1))) float *)sd.vext)[parity * n + i0 + min(tid, W - 1)];
     // kick weights of column tid from its shift in rows
     auto kick_weights = [&](double sh) {
         const double fl = floor(sh);
@@ -307,7 +311,7 @@ __device__ __forceinline__ void step32c_unit(const SimDev &sd, const Unit &u, in
     if (tid < W) {
         const double ic = (double)(i0 + tid);
         sh_xy[tid] = make_float2((float)fma(ic, sd.axi, sd.ax0), (float)fma(ic, sd.cyi, sd.cy0));
-        if constexpr (!WAITW) kick_weights(shift);
+        if constexpr (WAKE != WAKE_EXTERNAL) kick_weights(shift);
     }
     if constexpr (ROT == 1) {
         // RF kick of column i pulls along p from p + dtheta*q_i: shift tk*(q_min/dq + i) rows
@@ -456,6 +460,9 @@ __device__ __forceinline__ void step32c_unit(const SimDev &sd, const Unit &u, in
                 }
             }
         }
+    }
+    if constexpr (WAKE == WAKE_EXTERNAL && !WAITW) {
+        if (tid < W) kick_weights((double)vcol * sd.kick);
     }
     __syncthreads();
     if constexpr (WAITW) {
