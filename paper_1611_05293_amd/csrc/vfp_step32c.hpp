@@ -91,6 +91,17 @@ __device__ __forceinline__ int mad_i24(int a, int b, int c)
     return r;
 }
 
+// The value of v in the lane that DPP control CTRL selects (every lane
+// active; FP64 moved as two 32-bit halves)
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double v)
+{
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)b, CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xF, 0xF, false);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+
 // LDS byte address of a pointer into the workgroup's shared memory
 __device__ __forceinline__ unsigned lds_addr(const void *p)
 {
@@ -589,15 +600,31 @@ __device__ __forceinline__ void step32c_unit(const SimDev &sd, const Unit &u, in
         }
     }
     __syncthreads();
-    // FP64 column sums: g threads per column, each adding every g-th partial
-    // of its column, then a reduction over the g lanes (fixed order)
+    // FP64 column sums: g = 2^lg threads per column, each adding every g-th
+    // partial of its column in order (loads issued four at a time), then a
+    // reduction over the g lanes in a fixed order: lanes 1 and 2 apart, the
+    // other quad of the half-row and the other half of the row by DPP moves,
+    // the other rows by lane permutes
     {
-        const int g = W <= 4 ? 64 : W <= 8 ? 32 : W <= 16 ? 16 : W <= 32 ? 8 : 4;
-        const int c = tid / g, sub = tid - c * g;
+        const int lg = W <= 4 ? 6 : W <= 8 ? 5 : W <= 16 ? 4 : W <= 32 ? 3 : 2;
+        const int g = 1 << lg, c = tid >> lg, sub = tid & (g - 1), cnt = nb * 64;
         double t = 0.0;
-        if (c < W)
-            for (int k = sub; k < nb * 64; k += g) t += (double)Sp[c * nb * 64 + k];
-        for (int off = g >> 1; off > 0; off >>= 1) t += __shfl_xor(t, off, 64);
+        if (c < W) {
+            const float *pp = Sp + c * cnt;
+            for (int k = sub; k < cnt; k += 4 * g) {
+                float a[4];
+#pragma unroll
+                for (int q = 0; q < 4; ++q) a[q] = pp[min(k + q * g, cnt - 1)];   // in bounds, no branch
+#pragma unroll
+                for (int q = 0; q < 4; ++q) t += k + q * g < cnt ? (double)a[q] : 0.0;
+            }
+        }
+        t += dpp_f64<0xB1>(t);                      // quad_perm 1,0,3,2
+        t += dpp_f64<0x4E>(t);                      // quad_perm 2,3,0,1
+        if (g >= 8) t += dpp_f64<0x141>(t);         // row_half_mirror
+        if (g >= 16) t += dpp_f64<0x140>(t);        // row_mirror
+        if (g >= 32) t += __shfl_xor(t, 16, 64);
+        if (g >= 64) t += __shfl_xor(t, 32, 64);
         if (c < W && sub == 0) store_cs<COH>(cs_next + i0 + c, t);
     }
     if constexpr (MOM) {
