@@ -271,7 +271,9 @@ int vfp_batch_get_raw(vfp_batch *b, int32_t i, void *out, double *s);
  * kernel does not take (n % 4 != 0, rotation source more than 2 cells away)
  * use the generic kernel either way.  A new batch uses cells_per_unit 8192
  * (1024 for VFP_FP64 and 2048 for VFP_FIXED, whose strips take 16 bytes per
- * cell of LDS), graph replay, and staged = 2 for batches of at most 2 Mi
+ * cell of LDS; for the FP32-storage forms narrowed while the batch would
+ * have fewer than 2560 work units, down to strips of two columns on its
+ * largest grid), graph replay, and staged = 2 for batches of at most 2 Mi
  * cells per tick (a separate wake launch would sit on the tick's critical
  * path) or staged = 1 above; 0 restores the default cells.
  * Synchronises the stream and prepares the work layout. */

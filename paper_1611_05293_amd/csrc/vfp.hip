@@ -364,6 +364,36 @@ int upload_vec(vfp_batch *b, T *&dev, size_t &cap, const std::vector<T> &v)
 bool staged_wake(const vfp_batch *b, const Phase &ph) { return is_fp32_storage(b->precision) && ph.fast && ph.wake; }
 bool fused_tick(const vfp_batch *b, const Phase &ph) { return staged_wake(b, ph) && b->staged == kStagedFused; }
 
+// Cells per work unit of a batch left at its default: the precision's
+// default, narrowed for the FP32-storage forms while the batch would have
+// fewer work units than about two rounds of resident workgroups
+// (kTargetUnits), down to strips of two columns on its largest grid.  A small
+// batch runs latency-bound, and more, narrower strips spread it over more
+// compute units (single 256^2 and 512^2 simulations and the 64-simulation
+// 256^2 scan each about 6 % faster per tick); the 200-simulation scan has
+// 10,400 units at the default and keeps it.
+constexpr size_t kTargetUnits = 2560;
+int auto_cells(const vfp_batch *b)
+{
+    const int def = default_cells(b->precision);
+    if (!is_fp32_storage(b->precision)) return def;
+    int nmax = 0;
+    for (const HostSim &h : b->hs) nmax = std::max(nmax, h.p.n);
+    int cells = def;
+    for (const int c : {8192, 6144, 4096, 3072, 2048, 1536, 1024, 768, 512, 384, 256, 192, 128, 96, 64, 48, 32, 16}) {
+        if (c > def) continue;
+        if (c < 2 * nmax) break;                  // strips of at least two columns
+        cells = c;
+        size_t units = 0;
+        for (const HostSim &h : b->hs) {
+            const int n = h.p.n, w = choose_strip_c(n, c, b->rotation, h.halo);
+            units += (size_t)((n + w - 1) / w);
+        }
+        if (units >= kTargetUnits) break;
+    }
+    return cells;
+}
+
 // Units of the simulations in `sims`, appended in dispatch order: block
 // k*kXcds + x of a launch runs on XCD x (the dispatcher deals blocks
 // round-robin).  Every XCD gets an equal share of each grid size's strips
@@ -1388,6 +1418,7 @@ int create_impl(const vfp_params *p, int32_t count, void *stream, void *ws, size
         rc = upload_psi(b, s, p[s].psi0, p[s].psi0 == nullptr);
         if (rc) return bail(rc);
     }
+    b->cells = auto_cells(b);
     rc = rebuild(b);
     if (rc) return bail(rc);
     if (hipStreamSynchronize(b->stream) != hipSuccess) return bail(fail(VFP_EDEVICE, "setup failed"));
@@ -1738,8 +1769,7 @@ void vfp_destroy(vfp_sim *sim) { free_batch(sim); }
 int vfp_batch_set_tuning(vfp_batch *b, int32_t cells_per_unit, int32_t use_graph, int32_t staged)
 {
     if (!b || cells_per_unit < 0) return fail(VFP_EINVAL, "invalid arguments");
-    const int def = default_cells(b->precision);
-    const int cells = cells_per_unit ? cells_per_unit : def;
+    const int cells = cells_per_unit ? cells_per_unit : auto_cells(b);
     if (cells * elem_size(b->precision) * 2 > 128 * 1024)
         return fail(VFP_EINVAL, "cells_per_unit too large for the workgroup's LDS");
     if (cells < 16) return fail(VFP_EINVAL, "cells_per_unit too small");
