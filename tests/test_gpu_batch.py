@@ -286,3 +286,29 @@ def test_record_rows_after_staged_ticks_match_oracle_series(precision, rotation)
             assert np.abs(r[:, k] - rec[:, k]).max() <= 2e-5 * scale, (i, k)
         assert np.abs(r[:, 6] - rec[:, 6]).max() <= 1e-4 * np.abs(rec[:, 6]).max(), i
     b.close()
+
+
+def test_small_batches_narrow_their_strips():
+    """A batch of the FP32-storage forms with fewer than 2560 work units at
+    the default 8192 cells per unit narrows its strips, down to two columns
+    on its largest grid; a batch with enough units, and the FP64 form, keep
+    their defaults; set_tuning(0) restores the narrowed value.  Results match
+    the oracle at the narrowed width."""
+    s = small_sim(n=256, steps=500, S=0.5, Pi=1.0, seed=11, lo=-8.0, hi=8.0)
+    b = vfp.Batch([vfp.sim_kwargs(s, precision="fp32")])
+    assert b.get_tuning()[0] == 512                  # two columns of the 256-row grid
+    b.set_tuning(8192, True)
+    assert b.get_tuning()[0] == 8192
+    b.set_tuning(0, True)
+    assert b.get_tuning()[0] == 512
+    b.step(20)
+    ref, _, _, _ = oracle_run(s, 20)
+    assert rel_l1(b.get_psi(0), ref) <= 1e-5
+    b.close()
+    b = vfp.Batch([vfp.sim_kwargs(s, precision="fp64")])
+    assert b.get_tuning()[0] == 1024                 # the FP64 form's own default
+    b.close()
+    # 110 simulations of 256 rows: 2640 units of 11 columns at the default
+    big = vfp.Batch([vfp.sim_kwargs(s, precision="fp16")] * 110)
+    assert big.get_tuning()[0] == 8192
+    big.close()
