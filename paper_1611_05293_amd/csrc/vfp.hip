@@ -675,26 +675,33 @@ void launch_step32c_m(vfp_batch *b, const Target &t, int parity, bool mom)
     launch_step32c_t<K, WAKE, CL, ROT>(b, t, parity);
 }
 
-template <int K, bool CL, int ROT, int WK>
+template <int K, bool CL, int ROT, int WK, bool MOM>
 void launch_tick32_t(vfp_batch *b, const Target &t, int parity)
 {
     static int cur = 0;
-    lds_limit(tick32_kernel<K, CL, ROT, WK>, t.lds_step, cur);
-    hipLaunchKernelGGL((tick32_kernel<K, CL, ROT, WK>), dim3((unsigned)t.nitems), dim3(kThreads), t.lds_step, t.st,
-                       b->d_sd, t.items, t.nitems, parity, b->d_done, b->count, b->d_flag);
+    lds_limit(tick32_kernel<K, CL, ROT, WK, MOM>, t.lds_step, cur);
+    hipLaunchKernelGGL((tick32_kernel<K, CL, ROT, WK, MOM>), dim3((unsigned)t.nitems), dim3(kThreads), t.lds_step,
+                       t.st, b->d_sd, t.items, t.nitems, parity, b->d_done, b->count, b->d_flag);
+}
+
+template <int K, bool CL, int ROT, int WK>
+void launch_tick32_m(vfp_batch *b, const Target &t, int parity, bool mom)
+{
+    if (mom) launch_tick32_t<K, CL, ROT, WK, true>(b, t, parity);
+    else launch_tick32_t<K, CL, ROT, WK, false>(b, t, parity);
 }
 
 template <int K, bool CL, int ROT>
-void launch_tick32_w(vfp_batch *b, const Target &t, int parity)
+void launch_tick32_w(vfp_batch *b, const Target &t, int parity, bool mom)
 {
-    if (b->precision == VFP_MIXED_FP16) launch_tick32_t<K, CL, ROT, TW_FP16>(b, t, parity);
-    else if (b->precision == VFP_MIXED_BF16) launch_tick32_t<K, CL, ROT, TW_BF16>(b, t, parity);
-    else launch_tick32_t<K, CL, ROT, TW_VEC>(b, t, parity);
+    if (b->precision == VFP_MIXED_FP16) launch_tick32_m<K, CL, ROT, TW_FP16>(b, t, parity, mom);
+    else if (b->precision == VFP_MIXED_BF16) launch_tick32_m<K, CL, ROT, TW_BF16>(b, t, parity, mom);
+    else launch_tick32_m<K, CL, ROT, TW_VEC>(b, t, parity, mom);
 }
 
 // the step launch of a tick: kernel by storage type, wake mode, layout and tick form
-// (mom: the staged split-tick step also leaves the new state's per-column
-// moments; the caller reads *mom_done to know whether it did)
+// (mom: the staged step of either tick form also leaves the new state's
+// per-column moments; the caller reads *mom_done to know whether it did)
 template <typename T, int K, int WAKE>
 void launch_step_w(vfp_batch *b, const Phase &ph, const Target &t, int parity, bool mom, bool *mom_done)
 {
@@ -702,12 +709,13 @@ void launch_step_w(vfp_batch *b, const Phase &ph, const Target &t, int parity, b
         if (ph.fast) {
             if (WAKE == WAKE_EXTERNAL && b->staged == kStagedFused) {
                 if (b->rotation) {
-                    if (b->clamp) launch_tick32_w<K, true, 1>(b, t, parity);
-                    else launch_tick32_w<K, false, 1>(b, t, parity);
+                    if (b->clamp) launch_tick32_w<K, true, 1>(b, t, parity, mom);
+                    else launch_tick32_w<K, false, 1>(b, t, parity, mom);
                 } else {
-                    if (b->clamp) launch_tick32_w<K, true, 0>(b, t, parity);
-                    else launch_tick32_w<K, false, 0>(b, t, parity);
+                    if (b->clamp) launch_tick32_w<K, true, 0>(b, t, parity, mom);
+                    else launch_tick32_w<K, false, 0>(b, t, parity, mom);
                 }
+                if (mom_done) *mom_done = mom;
             } else {
                 if (b->rotation) {
                     if (b->clamp) launch_step32c_m<K, WAKE, true, 1>(b, t, parity, mom);

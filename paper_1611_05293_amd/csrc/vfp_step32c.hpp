@@ -656,7 +656,9 @@ enum TickWake { TW_VEC = 0, TW_FP16 = 1, TW_BF16 = 2 };
 // One tick of a batch in one launch.  The grid walks one list of items: the
 // wake tiles of every simulation first (w < 0, tile index in i0), then the
 // work units (w > 0, nu = the simulation's wake tile count), with empty
-// slots (w == 0) between the two parts.  A wake tile computes its part of
+// slots (w == 0) between the two parts (with MOM, on a tick followed by a
+// record row, the units also leave the new state's per-column moments, as
+// the split tick's step does).  A wake tile computes its part of
 // the wake V_t and the factor s_t of the current state from its column sums
 // (made by the previous launch; Sec. II.B, Eq. "wakepotential"), stores them
 // through to the coherent level, waits for the stores and counts itself in
@@ -668,7 +670,7 @@ enum TickWake { TW_VEC = 0, TW_FP16 = 1, TW_BF16 = 2 };
 // kWakeSpinLimit polls (about a second, far beyond any tick) sets *flag
 // instead, reported by the host as a device error, and once it is set no unit
 // waits any more, so every launch finishes.
-template <int K, bool CLAMP, int ROT, int WK>
+template <int K, bool CLAMP, int ROT, int WK, bool MOM = false>
 __global__ __launch_bounds__(kThreads) void tick32_kernel(const SimDev *__restrict__ sims,
                                                           const Unit *__restrict__ items, int nitems, int parity,
                                                           unsigned *__restrict__ ready, int count,
@@ -680,8 +682,8 @@ __global__ __launch_bounds__(kThreads) void tick32_kernel(const SimDev *__restri
     if (u.w == 0) return;                     // empty slot
     const SimDev &sd = sims[u.sim];
     if (u.w > 0) {
-        step32c_unit<K, WAKE_EXTERNAL, CLAMP, ROT, false, false, true>(sd, u, parity, ready + parity * count + u.sim,
-                                                                      u.nu, flag);
+        step32c_unit<K, WAKE_EXTERNAL, CLAMP, ROT, false, MOM, true>(sd, u, parity, ready + parity * count + u.sim,
+                                                                    u.nu, flag);
         return;
     }
     if (u.i0 == 0 && threadIdx.x == 0)
