@@ -567,7 +567,8 @@ int rebuild(vfp_batch *b)
             if (is_fp32_storage(b->precision)) {
                 for (int s : gs[g]) {
                     const int n = b->hs[s].p.n;
-                    const int nt = b->precision == VFP_FP32 ? (n + 255) / 256 : ((n + 15) / 16 + 15) / 16;
+                    const int nt = b->precision == VFP_FP32 ? (n + kWakeVecRows - 1) / kWakeVecRows
+                                                            : ((n + 15) / 16 + 15) / 16;
                     for (int t = 0; t < nt; ++t) b->wtiles.push_back(WakeTile{s, t, 0, 0});
                     ph.lds_wake = std::max(ph.lds_wake, b->precision == VFP_FP32 ? wake_vec_lds(n) : wake_mfma_lds(n));
                 }

@@ -1047,14 +1047,23 @@ __global__ __launch_bounds__(kThreads) void wake_mfma2_kernel(const SimDev *__re
 
 
 // Vector-ALU wake of the FP32 form, one workgroup per (simulation, tile of
-// 256 rows): V_i = S s sum_j w[i-j] rho_j with FP32 products and partial sums
-// over blocks of 32 consecutive j, added in FP64 (Sec. II.B; the same term
-// definition as the fused wake of the FP64/generic kernel).  LDS: rho (n
-// floats) and the tile's lag window (n + 255 floats).
-// LDS bytes of the vector-ALU wake: rho and a tile's lag window (FP32), then
-// (16-byte aligned) the block reduction
-__host__ __device__ inline size_t wake_vec_head(int n) { return ((size_t)(2 * n + 255) * sizeof(float) + 15) & ~(size_t)15; }
-__host__ __device__ inline size_t wake_vec_lds(int n) { return wake_vec_head(n) + kWaves * sizeof(double); }
+// kWakeVecRows rows, one per lane): V_i = S s sum_j w[i-j] rho_j with FP32
+// products and partial sums over blocks of 32 consecutive j, added in FP64;
+// each wave takes a quarter of the j range and the four quarters are added
+// in order (Sec. II.B; the same term definition as the fused wake of the
+// FP64/generic kernel).  LDS: rho (n floats) and the tile's lag window
+// (n + kWakeVecRows - 1 floats), then (16-byte aligned) the charge's wave
+// sums and the quarters' partial wakes.  Small tiles keep the wake short on
+// the one-launch tick of a single simulation, whose units wait for it.
+constexpr int kWakeVecRows = 64;
+__host__ __device__ inline size_t wake_vec_head(int n)
+{
+    return ((size_t)(2 * n + kWakeVecRows - 1) * sizeof(float) + 15) & ~(size_t)15;
+}
+__host__ __device__ inline size_t wake_vec_lds(int n)
+{
+    return wake_vec_head(n) + (size_t)kWaves * (1 + kWakeVecRows) * sizeof(double);
+}
 
 template <bool COH = false, bool OUTCOH = false>
 __device__ void wake_vec_tile(const SimDev &sd, int tile, int parity)
@@ -1062,10 +1071,11 @@ __device__ void wake_vec_tile(const SimDev &sd, int tile, int parity)
     extern __shared__ __align__(16) unsigned char smem_raw[];
     const int n = sd.n, tid = threadIdx.x, lane = tid & 63;
     const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
-    const int i0 = 256 * tile;
+    const int i0 = kWakeVecRows * tile;
     float *rho = (float *)smem_raw;
     float *lag = rho + n;                              // lag[k] = w[i0 + k - (n - 1)]
     double *red = (double *)(smem_raw + wake_vec_head(n));
+    double *wpart = red + kWaves;                      // [kWaves][kWakeVecRows] partial wakes
     typedef const __attribute__((address_space(1))) double gdouble;
     typedef const __attribute__((address_space(1))) float gfloat;
     const double *cs = sd.colsum[parity];
@@ -1081,8 +1091,7 @@ __device__ void wake_vec_tile(const SimDev &sd, int tile, int parity)
             if (k < n) rho[k] = (float)(sd.dp * v[q]);
         }
     }
-#pragma unroll 4
-    for (int k = tid; k < n + 255; k += kThreads) {
+    for (int k = tid; k < n + kWakeVecRows - 1; k += kThreads) {
         const int ix = i0 + k;                         // wl32 index = lag + n - 1
         lag[k] = ix <= 2 * n - 2 ? wl[ix] : 0.0f;
     }
@@ -1092,18 +1101,26 @@ __device__ void wake_vec_tile(const SimDev &sd, int tile, int parity)
     part = red[0];
     for (int k = 1; k < kWaves; ++k) part += red[k];
     const double s = sd.renorm ? sd.Q0 / (part * sd.dq * sd.dp) : 1.0;
-    const int i = i0 + tid;
+    // row i = i0 + lane; wave wv sums j over its quarter [ja, jz) in FP32 blocks of 32
+    const int i = i0 + lane;
+    double acc = 0.0;
     if (i < n) {
-        const float *lw = lag + tid + n - 1;           // lw[-j] = w[i - j]
-        double acc = 0.0;
-        for (int jb = 0; jb < n; jb += 32) {
+        const float *lw = lag + lane + n - 1;          // lw[-j] = w[i - j]
+        const int qn = (n + kWaves - 1) / kWaves, ja = wv * qn, jz = min(n, ja + qn);
+        for (int jb = ja; jb < jz; jb += 32) {
             float a32 = 0.0f;
-            const int je = jb + 32 < n ? jb + 32 : n;
+            const int je = jb + 32 < jz ? jb + 32 : jz;
 #pragma unroll 8
             for (int j = jb; j < je; ++j) a32 = fmaf(lw[-j], rho[j], a32);
             acc += a32;
         }
-        store_wake_f<OUTCOH>(sd.vext + parity * n + i, (float)(sd.S * s * acc));
+    }
+    wpart[wv * kWakeVecRows + lane] = acc;
+    __syncthreads();
+    if (wv == 0 && i < n) {
+        const double v = (wpart[lane] + wpart[kWakeVecRows + lane]) +
+                         (wpart[2 * kWakeVecRows + lane] + wpart[3 * kWakeVecRows + lane]);
+        store_wake_f<OUTCOH>(sd.vext + parity * n + i, (float)(sd.S * s * v));
     }
     if (tile == 0 && tid == 0) store_wake_d<OUTCOH>(sd.sext + parity, s);
 }
