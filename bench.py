@@ -240,7 +240,8 @@ def main():
         print(json.dumps(d))
         return
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        print(json.dumps({"error": "the benchmark runs on one GPU; --gpus must be 1 (a batch's simulations "
+                                   "are independent and shard across GPUs by simulation, with no exchange per tick)"}))
         sys.exit(2)
 
     import torch                          # device memory and the stream only
